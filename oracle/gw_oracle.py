@@ -1,0 +1,530 @@
+"""FP64 CPU oracle for the CNT-GW hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module:
+only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import or call it.  It shares no code, constant or helper
+with the HIP library.
+
+It is the plain, slow, materialised form of what the paper computes:
+
+* every N x M cost is materialised in float64, directly as a sum of squared
+  coordinate differences (never through the expanded dot product the GPU
+  uses);
+* every log-sum-exp is a max-shifted reduction over a full row or column;
+* the algorithms run in the paper's order and notation.
+
+Readings of passages where the paper is silent or garbled are listed in the
+design notes; each function states the passage it follows.
+
+Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
+    centre, lifted_loss, constant_c, quartic_loss  - brute force / closed form
+    sinkhorn                                      - unique EOT optimum, textbook
+                                                    scaling iteration, separable
+                                                    costs, N = 1
+    cnt_gw                                        - Entropic-GW and Kernel-GW
+                                                    agreement, permutation
+                                                    enumeration, rigid motion,
+                                                    monotone objective, Thm 4.5
+    landmark_lift, kernel_from_cost, kernel_pca   - full-rank exact embedding
+    grad_positions, grad_weights                  - quartic-form envelope,
+                                                    central finite differences,
+                                                    translation / rotation
+                                                    invariants
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Features
+# --------------------------------------------------------------------------
+
+
+def centre(x: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Centred embedding phi(x) = x - x_alpha of the squared-norm example
+    (Section 3, "Example": GW-embeddings for squared Euclidean costs), with
+    x_alpha = sum_i w_i x_i.  Also used to re-centre any embedding so that
+    sum_i a_i X_i = 0 as Section 5 requires of the inputs to CNT-GW."""
+    x = np.asarray(x, dtype=np.float64)
+    return x - (w[:, None] * x).sum(axis=0)[None, :]
+
+
+def sqdist(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Pairwise squared Euclidean distances, summed coordinate by
+    coordinate (no expansion into norms and dot products)."""
+    out = np.zeros((x.shape[0], y.shape[0]))
+    for k in range(x.shape[1]):
+        diff = x[:, k][:, None] - y[:, k][None, :]
+        out += diff * diff
+    return out
+
+
+def power_cost(x: np.ndarray, y: np.ndarray, p: float) -> np.ndarray:
+    """c(x, y) = |x - y|^p, conditionally of negative type for 0 < p <= 2
+    (Section 2, "Embeddable Costs")."""
+    d2 = sqdist(x, y)
+    if p == 2.0:
+        return d2
+    return np.power(d2, 0.5 * p)
+
+
+def cnt_kernel(c_xy: np.ndarray, c_x0: np.ndarray, c_0y: np.ndarray) -> np.ndarray:
+    """k(x, x') = (c(x, x0) + c(x0, x') - c(x, x')) / 2
+    (Section 2, Proposition on CNT costs inducing positive kernels)."""
+    return 0.5 * (c_x0[:, None] + c_0y[None, :] - c_xy)
+
+
+def kernel_from_cost(c: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Algorithm 4 (Kernel), Appendix B.2: kernel from a CNT cost matrix with
+    base index 1, then weighted double centring.  The centring step's indices
+    are garbled in the paper; it is read as K <- (I - 1 w^T) K (I - w 1^T)."""
+    k = cnt_kernel(c, c[:, 0], c[0, :])
+    col = w @ k                      # sum_i w_i K_ij
+    row = k @ w                      # sum_j w_j K_ij
+    tot = w @ k @ w
+    return k - col[None, :] - row[:, None] + tot
+
+
+def kernel_pca(k: np.ndarray, dim: int, rel_floor: float = 1e-12):
+    """Kernel PCA (Appendix B.2): top-D eigenpairs of the centred kernel,
+    X = V sqrt(Lambda).  Eigenvalues below rel_floor * lambda_max are
+    dropped (their feature columns are zero)."""
+    lam, vec = np.linalg.eigh(k)
+    order = np.argsort(lam)[::-1][:dim]
+    lam, vec = lam[order], vec[:, order]
+    keep = lam > rel_floor * max(lam[0], 0.0)
+    lam = np.where(keep, lam, 0.0)
+    vec = np.where(keep[None, :], vec, 0.0)
+    return lam, vec
+
+
+@dataclass
+class Landmarks:
+    """Frozen landmark kernel PCA: positions, weights, eigenpairs."""
+
+    pts: np.ndarray      # (L, d)
+    w: np.ndarray        # (L,)
+    lam: np.ndarray      # (D,)
+    vec: np.ndarray      # (L, D)
+    p: float
+
+
+def fit_landmarks(pts: np.ndarray, p: float, dim: int) -> Landmarks:
+    """Landmark kernel PCA: Algorithm 4 on the landmark cost matrix with
+    uniform landmark weights, then the top-D eigenpairs."""
+    w = np.full(pts.shape[0], 1.0 / pts.shape[0])
+    k = kernel_from_cost(power_cost(pts, pts, p), w)
+    lam, vec = kernel_pca(k, dim)
+    return Landmarks(np.array(pts, dtype=np.float64), w, lam, vec, p)
+
+
+def kernel_proj(x: np.ndarray, lm: Landmarks) -> np.ndarray:
+    """Algorithm 13 (Kernel-Proj): Pi(x)_d = Lambda_d^{-1/2} sum_l k(x, x_l)
+    V_ld, with k the landmark-centred CNT kernel (the kernel of the CNT
+    proposition, centred against the landmark measure as in Algorithm 4)."""
+    c_xl = power_cost(x, lm.pts, lm.p)               # (N, L)
+    c_ll = power_cost(lm.pts, lm.pts, lm.p)          # (L, L)
+    x0 = lm.pts[0:1]
+    c_x0 = power_cost(x, x0, lm.p)[:, 0]
+    c_l0 = power_cost(lm.pts, x0, lm.p)[:, 0]
+    k_xl = cnt_kernel(c_xl, c_x0, c_l0)              # (N, L)
+    k_ll = cnt_kernel(c_ll, c_l0, c_l0)              # (L, L)
+    w = lm.w
+    kc = (k_xl - (k_xl @ w)[:, None] - (w @ k_ll)[None, :] + w @ k_ll @ w)
+    inv = np.where(lm.lam > 0, 1.0 / np.sqrt(np.where(lm.lam > 0, lm.lam, 1.0)), 0.0)
+    return (kc @ lm.vec) * inv[None, :]
+
+
+def kernel_proj_jacobian(x: np.ndarray, lm: Landmarks) -> np.ndarray:
+    """Gradient of Algorithm 13's map (Appendix B.6, "Approximation with
+    Kernel PCA"): J[n, d, :] = Lambda_d^{-1/2} sum_l grad_x k(x_n, x_l) V_ld.
+    For c = |x - x'|^p, grad_x c = p |x - x'|^{p-2} (x - x'), taken as 0 at
+    x = x' (the subgradient that central differences return for p = 1)."""
+    n, dim_in = x.shape
+    diff = x[:, None, :] - lm.pts[None, :, :]                 # (N, L, d)
+    r2 = (diff * diff).sum(-1)
+    if lm.p == 2.0:
+        coef = np.full_like(r2, 2.0)
+    else:
+        safe = np.where(r2 > 0, r2, 1.0)
+        coef = np.where(r2 > 0, lm.p * np.power(safe, 0.5 * lm.p - 1.0), 0.0)
+    grad_c = coef[:, :, None] * diff                          # (N, L, d)
+    # centred kernel: k~ = -1/2 [c(x, x_l) - sum_m w_m c(x, x_m)] + const(x_l)
+    mean_grad = np.einsum("m,nmk->nk", lm.w, grad_c)
+    grad_k = -0.5 * (grad_c - mean_grad[:, None, :])          # (N, L, d)
+    inv = np.where(lm.lam > 0, 1.0 / np.sqrt(np.where(lm.lam > 0, lm.lam, 1.0)), 0.0)
+    return np.einsum("nlk,ld->ndk", grad_k, lm.vec) * inv[None, :, None]
+
+
+def landmark_features(x: np.ndarray, a: np.ndarray, lm: Landmarks) -> np.ndarray:
+    """Lifted features of all points: Nystrom map through the frozen
+    landmarks, then re-centred with the weights a (Section 5 requires
+    sum_i a_i X_i = 0)."""
+    return centre(kernel_proj(x, lm), a)
+
+
+def choose_landmarks(n: int, n_landmarks: int, seed: int) -> np.ndarray:
+    """Indices of the landmark subset: the first n_l entries of a seeded
+    permutation (the same rule the library documents)."""
+    perm = np.random.default_rng(seed).permutation(n)
+    return np.sort(perm[: min(n_landmarks, n)])
+
+
+# --------------------------------------------------------------------------
+# Entropic OT
+# --------------------------------------------------------------------------
+
+
+def lse(v: np.ndarray, axis: int) -> np.ndarray:
+    """Max-shifted log-sum-exp along one axis."""
+    mx = np.max(v, axis=axis, keepdims=True)
+    mx = np.where(np.isfinite(mx), mx, 0.0)
+    return (mx + np.log(np.sum(np.exp(v - mx), axis=axis, keepdims=True))).squeeze(axis)
+
+
+def softmin_rows(b: np.ndarray, g: np.ndarray, c: np.ndarray, eps: float) -> np.ndarray:
+    """Sinkhorn operator over j (Appendix A.1, Eq. sinkhorn_operators):
+    -eps log sum_j exp(log b_j + (g_j - C_ij) / eps)."""
+    return -eps * lse(np.log(b)[None, :] + (g[None, :] - c) / eps, axis=1)
+
+
+def softmin_cols(a: np.ndarray, f: np.ndarray, c: np.ndarray, eps: float) -> np.ndarray:
+    """Sinkhorn operator over i: -eps log sum_i exp(log a_i + (f_i - C_ij)/eps)."""
+    return -eps * lse(np.log(a)[:, None] + (f[:, None] - c) / eps, axis=0)
+
+
+def sinkhorn(a, b, c, eps, n_iter, f0=None, g0=None, symmetric=True):
+    """Algorithm 2 (Sinkhorn) or Algorithm 3 (Sinkhorn-symm), Appendix B.1,
+    in the log domain.  Symmetric: both half-steps read iterate n.
+    Alternating: the g update reads the new f."""
+    f = np.zeros(len(a)) if f0 is None else np.array(f0, dtype=np.float64)
+    g = np.zeros(len(b)) if g0 is None else np.array(g0, dtype=np.float64)
+    for _ in range(n_iter):
+        if symmetric:
+            tf = softmin_rows(b, g, c, eps)
+            tg = softmin_cols(a, f, c, eps)
+            f, g = 0.5 * (f + tf), 0.5 * (g + tg)
+        else:
+            f = softmin_rows(b, g, c, eps)
+            g = softmin_cols(a, f, c, eps)
+    return f, g
+
+
+def plan(a, b, f, g, c, eps):
+    """Coupling from dual potentials (Section 2, Eq. sinkhorn_pi):
+    pi_ij = a_i b_j exp((f_i + g_j - C_ij) / eps)."""
+    return a[:, None] * b[None, :] * np.exp((f[:, None] + g[None, :] - c) / eps)
+
+
+def marginal_error(pi, a, b) -> float:
+    """Err(pi) = |pi 1 - a|_1 + |pi^T 1 - b|_1 (Appendix A.1)."""
+    return float(np.abs(pi.sum(1) - a).sum() + np.abs(pi.sum(0) - b).sum())
+
+
+def kl_divergence(pi, a, b) -> float:
+    """KL(pi | a x b) = sum pi log(pi / (a b)) (Section 2, EOT problem)."""
+    ab = a[:, None] * b[None, :]
+    mask = pi > 0
+    return float(np.sum(pi[mask] * np.log(pi[mask] / ab[mask])))
+
+
+# --------------------------------------------------------------------------
+# CNT-GW (Algorithm 1)
+# --------------------------------------------------------------------------
+
+
+def eps_schedule(eps_start: float, eps_end: float, n_outer: int) -> np.ndarray:
+    """Outer temperature schedule.  The paper fixes eps; an annealed
+    schedule is read as geometric, eps_t = eps_0 (eps_end/eps_0)^(t/(T-1))."""
+    if n_outer <= 1 or eps_start == eps_end:
+        return np.full(max(n_outer, 1), float(eps_start))
+    t = np.arange(n_outer) / (n_outer - 1)
+    return eps_start * np.power(eps_end / eps_start, t)
+
+
+def lift(v: np.ndarray) -> np.ndarray:
+    """[v, |v|^2 / 2] (Algorithm 1, lifted features)."""
+    return np.concatenate([v, 0.5 * np.sum(v * v, axis=1, keepdims=True)], axis=1)
+
+
+@dataclass
+class GWResult:
+    f: np.ndarray            # final potentials, Algorithm 1 convention
+    g: np.ndarray
+    gamma: np.ndarray        # Gamma_T = X^T pi Y
+    gamma_prev: np.ndarray   # Gamma_{T-1}, the map the final pi was built with
+    pi: np.ndarray           # final coupling
+    eps: float               # last outer temperature
+    history: list = field(default_factory=list)
+
+
+def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
+           f0=None, g0=None, symmetric=True, record=False, inner_tol=None) -> GWResult:
+    """Algorithm 1 (CNT-GW), Section 5, with a fixed number of outer steps.
+
+    Per outer step t: Zbar_j = [Gamma_t Y_j, |Y_j|^2/2]; the squared-norm
+    cost between lifted features is materialised; Sinkhorn runs at eps_t/8
+    warm-started from the previous potentials (Appendix B.1, warm start);
+    then X~_j = sum_i a_i X_i exp(8/eps (f_i + g_j - |Xbar_i - Zbar_j|^2)) and
+    Gamma_{t+1} = sum_j b_j X~_j Y_j^T.  With inner_tol set, each inner solve
+    runs to that marginal error instead of n_inner iterations."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    gamma = np.zeros((X.shape[1], Y.shape[1])) if gamma0 is None else np.array(gamma0, np.float64)
+    xbar = lift(X)
+    f = np.zeros(len(a)) if f0 is None else np.array(f0, np.float64)
+    g = np.zeros(len(b)) if g0 is None else np.array(g0, np.float64)
+    hist = []
+    gamma_prev = gamma
+    pi = None
+    eps_list = eps_schedule(eps_start, eps_end, n_outer)
+    for eps in eps_list:
+        zbar = np.concatenate([Y @ gamma.T, 0.5 * np.sum(Y * Y, axis=1, keepdims=True)], axis=1)
+        cbar = sqdist(xbar, zbar)
+        epsp = eps / 8.0
+        if inner_tol is None:
+            f, g = sinkhorn(a, b, cbar, epsp, n_inner, f, g, symmetric)
+        else:
+            f, g = sinkhorn_converged(a, b, cbar, epsp, f, g, tol=inner_tol)
+        expo = np.exp((f[:, None] + g[None, :] - cbar) / epsp)
+        xt = expo.T @ (a[:, None] * X)          # X~_j = sum_i a_i X_i expo_ij
+        new_gamma = (b[:, None] * xt).T @ Y
+        pi = a[:, None] * b[None, :] * expo
+        if record:
+            hist.append({"eps": float(eps), "gamma": new_gamma.copy(),
+                         "pi": pi.copy(), "f": f.copy(), "g": g.copy()})
+        gamma_prev, gamma = gamma, new_gamma
+    return GWResult(f, g, gamma, gamma_prev, pi, float(eps_list[-1]), hist)
+
+
+# --------------------------------------------------------------------------
+# Losses
+# --------------------------------------------------------------------------
+
+
+def constant_c(X, Y, a, b) -> float:
+    """C(alpha, beta) of Lemma C.1 by its O(N^2) definition:
+    sum a a |x - x'|^4 + sum b b |y - y'|^4 - 4 (sum a |x|^2)(sum b |y|^2)."""
+    dx = sqdist(X, X)
+    dy = sqdist(Y, Y)
+    return float(a @ (dx * dx) @ a + b @ (dy * dy) @ b
+                 - 4.0 * (a @ np.sum(X * X, 1)) * (b @ np.sum(Y * Y, 1)))
+
+
+def lifted_loss(X, Y, a, b, pi) -> float:
+    """Lemma C.1: L(pi) = C - 8 |sum pi x y^T|^2 - 4 sum pi |x|^2 |y|^2, for
+    centred features.  Equals the GW loss for any pi in Pi(a, b)."""
+    gam = X.T @ pi @ Y
+    nm = np.sum(X * X, 1)[:, None] * np.sum(Y * Y, 1)[None, :]
+    return constant_c(X, Y, a, b) - 8.0 * float(np.sum(gam * gam)) - 4.0 * float(np.sum(pi * nm))
+
+
+def quartic_loss_literal(cx, cy, pi) -> float:
+    """Eq. GW_loss by its definition, sum_ijkl (cX_ik - cY_jl)^2 pi_ij pi_kl
+    (small inputs only: N^2 M^2 terms)."""
+    diff = cx[:, None, :, None] - cy[None, :, None, :]        # (i, j, k, l)
+    return float(np.einsum("ijkl,ij,kl->", diff * diff, pi, pi))
+
+
+def quartic_loss(cx, cy, pi) -> float:
+    """Eq. GW_loss, exactly rearranged for any pi (no feasibility used):
+    r^T cX^2 r + c^T cY^2 c - 2 sum_ij pi_ij (cX pi cY)_ij with r, c the
+    marginals of pi itself."""
+    r = pi.sum(1)
+    c = pi.sum(0)
+    return float(r @ (cx * cx) @ r + c @ (cy * cy) @ c - 2.0 * np.sum(pi * (cx @ pi @ cy)))
+
+
+def egw_objective(X, Y, a, b, pi, eps) -> float:
+    """EGW objective L(pi) + eps KL(pi | a x b) (Section 2, Eq. entropic GW),
+    with L in the lifted form."""
+    return lifted_loss(X, Y, a, b, pi) + eps * kl_divergence(pi, a, b)
+
+
+def dual_function(X, Y, a, b, gamma, eps, tol=1e-15) -> float:
+    """Phi_eps(Gamma) = |Gamma|^2 + OT^Gamma_eps / 8 (proof of the dual-descent
+    proposition), with OT^Gamma_eps the EOT value for the bilinear cost
+    c_Gamma = -16 <Gamma, x y^T> - 4 |x|^2 |y|^2 (Remark C.2) at eps."""
+    c = -16.0 * (X @ gamma @ Y.T) - 4.0 * np.sum(X * X, 1)[:, None] * np.sum(Y * Y, 1)[None, :]
+    f, g = sinkhorn_converged(a, b, c, eps, tol=tol)
+    pi = plan(a, b, f, g, c, eps)
+    ot = float(np.sum(pi * c)) + eps * kl_divergence(pi, a, b)
+    return float(np.sum(gamma * gamma)) + ot / 8.0
+
+
+# --------------------------------------------------------------------------
+# Comparison algorithms used as pins
+# --------------------------------------------------------------------------
+
+
+def full_linearisation(cx, cy, pi):
+    """grad L(pi)_ij = 2 sum_kl (cX_ik - cY_jl)^2 pi_kl (primal-descent proof,
+    Appendix C), exactly rearranged for any pi."""
+    r = pi.sum(1)
+    c = pi.sum(0)
+    return 2.0 * ((cx * cx) @ r[:, None] + ((cy * cy) @ c)[None, :] - 2.0 * (cx @ pi @ cy))
+
+
+def entropic_gw(a, b, cx, cy, eps, n_outer, n_inner, pi0=None, inner_tol=None):
+    """Entropic-GW (Section 4.2, Eq. entropic_cgd_sequence): pi_{t+1} is the
+    EOT plan at eps for the cost grad L(pi_t), starting from a x b."""
+    pi = np.outer(a, b) if pi0 is None else pi0
+    out = []
+    for _ in range(n_outer):
+        c = full_linearisation(cx, cy, pi)
+        if inner_tol is None:
+            f, g = sinkhorn(a, b, c, eps, n_inner)
+        else:
+            f, g = sinkhorn_converged(a, b, c, eps, tol=inner_tol)
+        pi = plan(a, b, f, g, c, eps)
+        out.append(pi)
+    return out
+
+
+def kernel_gw(a, b, cx, cy, eps, n_outer, n_inner, inner_tol=None):
+    """Algorithm 5 (Kernel-GW), Appendix B.3: cost -4 K^X_ii K^Y_jj
+    - 16 sum_kl K^X_ik K^Y_jl pi_kl, symmetric Sinkhorn at eps."""
+    kx = kernel_from_cost(cx, a)
+    ky = kernel_from_cost(cy, b)
+    pi = np.outer(a, b)
+    out = []
+    for _ in range(n_outer):
+        c = -4.0 * np.diag(kx)[:, None] * np.diag(ky)[None, :] - 16.0 * (kx @ pi @ ky.T)
+        if inner_tol is None:
+            f, g = sinkhorn(a, b, c, eps, n_inner, symmetric=True)
+        else:
+            f, g = sinkhorn_converged(a, b, c, eps, tol=inner_tol, symmetric=True)
+        pi = plan(a, b, f, g, c, eps)
+        out.append(pi)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Gradients (Appendix B.6)
+# --------------------------------------------------------------------------
+
+
+def grad_features(X, Y, a, b, pi, gamma):
+    """Envelope gradient of GW_eps with respect to the lifted source
+    features (Appendix B.6): d/dX_i of the constant C of Lemma C.1 plus
+    sum_j pi_ij d/dX_i c_Gamma(X_i, Y_j), with c_Gamma of Remark C.2 and
+    Gamma, pi held at the optimum.  Derivative of C written from its double
+    sum: 8 a_i sum_k a_k |X_i - X_k|^2 (X_i - X_k) - 8 a_i s_y X_i."""
+    n2 = np.sum(X * X, 1)
+    m2 = np.sum(Y * Y, 1)
+    s_y = float(b @ m2)
+    dx = sqdist(X, X)
+    wk = a[None, :] * dx                                      # a_k |X_i - X_k|^2
+    dc = 8.0 * a[:, None] * (wk.sum(1)[:, None] * X - wk @ X) - 8.0 * a[:, None] * s_y * X
+    dot = -16.0 * (pi @ Y) @ gamma.T - 8.0 * X * (pi @ m2)[:, None]
+    return dc + dot
+
+
+def grad_features_target(X, Y, a, b, pi, gamma):
+    """Same envelope gradient for the target features (roles swapped)."""
+    return grad_features(Y, X, b, a, pi.T, gamma.T)
+
+
+def chain_centre(gx_feat, w):
+    """Chain rule through re-centring X = P - sum_k w_k P_k:
+    dL/dP_i = G_i - w_i sum_k G_k."""
+    return gx_feat - w[:, None] * gx_feat.sum(0)[None, :]
+
+
+def grad_positions_sqeuclid(X, Y, a, b, pi, gamma):
+    """Position gradient for the squared Euclidean penalty (features are the
+    centred points, Section 3 example)."""
+    return chain_centre(grad_features(X, Y, a, b, pi, gamma), a)
+
+
+def grad_positions_power(x, X, Y, a, b, pi, gamma, lm: Landmarks):
+    """Position gradient through the frozen Nystrom map (Algorithm 12 with
+    Algorithm 13), including re-centring."""
+    gf = chain_centre(grad_features(X, Y, a, b, pi, gamma), a)   # (N, D)
+    jac = kernel_proj_jacobian(x, lm)                            # (N, D, d)
+    return np.einsum("nd,ndk->nk", gf, jac)
+
+
+def grad_positions_quartic(x, a, pi, cy, p=2.0):
+    """Independent pin: envelope gradient of Eq. GW_loss itself at fixed pi,
+    d/dx_i sum_ijkl (cX_ik - cY_jl)^2 pi_ij pi_kl
+      = 4 sum_k [cX_ik r_i r_k - (pi cY pi^T)_ik] grad_1 cX(x_i, x_k)."""
+    cx = power_cost(x, x, p)
+    r = pi.sum(1)
+    w = cx * r[:, None] * r[None, :] - pi @ cy @ pi.T
+    diff = x[:, None, :] - x[None, :, :]
+    r2 = (diff * diff).sum(-1)
+    if p == 2.0:
+        coef = np.full_like(r2, 2.0)
+    else:
+        safe = np.where(r2 > 0, r2, 1.0)
+        coef = np.where(r2 > 0, p * np.power(safe, 0.5 * p - 1.0), 0.0)
+    return 4.0 * np.einsum("ik,ik,ikd->id", w, coef, diff)
+
+
+def grad_weights(cx, cy, a, b, pi, eps, n_iter=20000):
+    """Weight gradient of GW_eps: by the Lagrangian of the EGW problem the
+    derivative along sum(da) = 0 is <F, da>, with F the EOT potential at eps
+    for the linearised cost grad L(pi*) = 2 sum_kl (cX - cY)^2 pi*_kl.
+    Returned centred (sum a_i F_i = 0); constants do not matter on the
+    simplex."""
+    c = full_linearisation(cx, cy, pi)
+    f, g = sinkhorn(a, b, c, eps, n_iter)
+    return f - a @ f
+
+
+# --------------------------------------------------------------------------
+# Converged solves (for finite differences and pins)
+# --------------------------------------------------------------------------
+
+
+def sinkhorn_converged(a, b, c, eps, f0=None, g0=None, tol=1e-14, max_iter=100000,
+                       symmetric=False):
+    """Run Sinkhorn until the marginal error of the plan is below tol, or
+    until it stops decreasing (the float64 rounding floor)."""
+    f = np.zeros(len(a)) if f0 is None else f0.copy()
+    g = np.zeros(len(b)) if g0 is None else g0.copy()
+    it = 0
+    best = np.inf
+    stall = 0
+    while it < max_iter:
+        f, g = sinkhorn(a, b, c, eps, 20, f, g, symmetric)
+        it += 20
+        err = marginal_error(plan(a, b, f, g, c, eps), a, b)
+        if err < tol:
+            break
+        if err < 0.5 * best:
+            best = err
+            stall = 0
+        else:
+            stall += 1
+            if stall >= 10 and err < 1e-12:
+                break
+    return f, g
+
+
+def cnt_gw_converged(a, b, X, Y, eps, gamma0=None, tol=1e-13, max_outer=5000,
+                     sink_tol=1e-14):
+    """Algorithm 1 with the paper's stopping rule |Gamma_t - Gamma_{t+1}| <= tol
+    and Sinkhorn solved to sink_tol at every outer step."""
+    gamma = np.zeros((X.shape[1], Y.shape[1])) if gamma0 is None else gamma0.copy()
+    xbar = lift(X)
+    f = np.zeros(len(a))
+    g = np.zeros(len(b))
+    epsp = eps / 8.0
+    pi = None
+    for _ in range(max_outer):
+        zbar = np.concatenate([Y @ gamma.T, 0.5 * np.sum(Y * Y, 1, keepdims=True)], 1)
+        cbar = sqdist(xbar, zbar)
+        f, g = sinkhorn_converged(a, b, cbar, epsp, f, g, tol=sink_tol)
+        pi = plan(a, b, f, g, cbar, epsp)
+        new_gamma = X.T @ pi @ Y
+        step = float(np.linalg.norm(new_gamma - gamma))
+        gamma = new_gamma
+        if step <= tol:
+            break
+    return gamma, pi, f, g

@@ -1,0 +1,172 @@
+"""Seeded generators for the five workloads of the hot path.
+
+Seeds follow ``1000 * config + repetition``.  Every array is float64; the GPU
+path casts to float32 itself.  The paper's own inputs are surface samples of
+3-D shapes (Table 1, 4k to 177k points, uniform weights); they are not
+available here, so Gaussian-mixture clouds of the same sizes stand in for
+them.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    """One GW instance: weighted source and target point sets plus settings."""
+
+    x: np.ndarray            # (N, dx) source points
+    a: np.ndarray            # (N,) source weights, positive, sum 1
+    y: np.ndarray            # (M, dy) target points
+    b: np.ndarray            # (M,) target weights, positive, sum 1
+    eps_start: float
+    eps_end: float
+    n_outer: int
+    n_inner: int
+    penalty: str = "sqeuclid"   # "sqeuclid" | "power"
+    p: float = 2.0              # exponent of |x - x'|^p for "power"
+    lifted_dim: int = 0         # D = E for "power" (0: raw dimension)
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.x.shape[0]
+
+    @property
+    def m(self) -> int:
+        return self.y.shape[0]
+
+
+def haar_rotation(rng: np.random.Generator, d: int) -> np.ndarray:
+    """Uniform (Haar) rotation in SO(d): QR of a Gaussian matrix with the
+    signs of R's diagonal moved into Q (Mezzadri 2007), then a reflection
+    fix so that det = +1."""
+    g = rng.standard_normal((d, d))
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def gmm_points(rng: np.random.Generator, n: int, means: np.ndarray,
+               sigma: float) -> np.ndarray:
+    """n samples of an equal-weight isotropic Gaussian mixture."""
+    k = rng.integers(0, means.shape[0], size=n)
+    return means[k] + sigma * rng.standard_normal((n, means.shape[1]))
+
+
+def uniform_weights(n: int) -> np.ndarray:
+    return np.full(n, 1.0 / n)
+
+
+def rotated_copy(rng: np.random.Generator, x: np.ndarray, noise: float,
+                 translate: bool) -> np.ndarray:
+    """y = R x + t + noise * xi with R Haar, t ~ U[-1,1]^d (if translate)."""
+    d = x.shape[1]
+    rot = haar_rotation(rng, d)
+    t = rng.uniform(-1.0, 1.0, size=d) if translate else np.zeros(d)
+    return x @ rot.T + t[None, :] + noise * rng.standard_normal(x.shape)
+
+
+def config1_plain(rep: int = 0, n: int = 512) -> Problem:
+    """Plain entropic GW, squared-Euclidean penalty: x ~ U[0,1]^2, y = source
+    rotated by a uniform angle plus N(0, 0.01^2) noise, uniform weights,
+    eps = 0.01, 20 outer x 50 symmetric Sinkhorn iterations."""
+    rng = np.random.default_rng(1000 * 1 + rep)
+    x = rng.uniform(0.0, 1.0, size=(n, 2))
+    theta = rng.uniform(0.0, 2.0 * np.pi)
+    rot = np.array([[np.cos(theta), -np.sin(theta)],
+                    [np.sin(theta), np.cos(theta)]])
+    y = x @ rot.T + 0.01 * rng.standard_normal((n, 2))
+    return Problem(x, uniform_weights(n), y, uniform_weights(n),
+                   0.01, 0.01, 20, 50, "sqeuclid", 2.0, 0, "plain-512",
+                   {"theta": theta})
+
+
+def _gmm_pair(seed: int, n: int, d: int, k: int, sigma: float,
+              noise: float) -> tuple[np.ndarray, np.ndarray]:
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, size=(k, d))
+    x = gmm_points(rng, n, means, sigma)
+    y = rotated_copy(rng, x, noise, translate=True)
+    return x, y
+
+
+def config2_fp32(rep: int = 0, n: int = 20_000, lifted_dim: int = 32) -> Problem:
+    """3-D 8-component mixture (means U[-1,1]^3, sigma 0.1); target = Haar
+    rotation + translation + N(0, 0.005^2) noise; |x - x'| penalty lifted to
+    D = 32; eps annealed 0.1 -> 0.005 over 30 outer steps, 100 inner."""
+    x, y = _gmm_pair(1000 * 2 + rep, n, 3, 8, 0.1, 0.005)
+    return Problem(x, uniform_weights(n), y, uniform_weights(n),
+                   0.1, 0.005, 30, 100, "power", 1.0, lifted_dim,
+                   f"gmm3d-{n}")
+
+
+def config3_scale(rep: int = 0, n: int = 200_000, lifted_dim: int = 64) -> Problem:
+    """Same generator as config 2 at N = M = 200,000 with D = 64."""
+    x, y = _gmm_pair(1000 * 3 + rep, n, 3, 8, 0.1, 0.005)
+    return Problem(x, uniform_weights(n), y, uniform_weights(n),
+                   0.1, 0.005, 30, 100, "power", 1.0, lifted_dim,
+                   f"gmm3d-{n}")
+
+
+def config4_requests(n_requests: int = 512, lo: int = 1_000, hi: int = 50_000,
+                     lifted_dim: int = 32, seed_base: int = 4000,
+                     rate: float = 1.0) -> list[tuple[float, Problem]]:
+    """Serving trace: sizes log-uniform in [lo, hi] drawn independently for
+    source and target, dimension 2 or 3 with probability 1/2 each, source and
+    target are independent samples of one 8-component mixture with the target
+    under a Haar rigid motion; eps = 0.01, 20 outer x 50 inner.  Arrival
+    times are a Poisson process of the given rate (requests per second)."""
+    trace_rng = np.random.default_rng(seed_base - 1)
+    gaps = trace_rng.exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for k in range(n_requests):
+        rng = np.random.default_rng(seed_base + k)
+        n = int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        m = int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        d = 2 if rng.uniform() < 0.5 else 3
+        means = rng.uniform(-1.0, 1.0, size=(8, d))
+        x = gmm_points(rng, n, means, 0.1)
+        y0 = gmm_points(rng, m, means, 0.1)
+        y = rotated_copy(rng, y0, 0.0, translate=True)
+        out.append((float(arrivals[k]),
+                    Problem(x, uniform_weights(n), y, uniform_weights(m),
+                            0.01, 0.01, 20, 50, "power", 1.0, lifted_dim,
+                            f"req{k}-{n}x{m}-d{d}")))
+    return out
+
+
+def config5_grad(rep: int = 0, n: int = 50_000, m: int = 30_000,
+                 lifted_dim: int = 64) -> Problem:
+    """d = 16, 16-component mixture (means U[-1,1]^16, sigma 0.1); source and
+    target are independent draws of the mixture (target under a rigid
+    motion); weights Dirichlet(1); |x - x'| lifted to D = 64; eps = 0.01,
+    20 outer x 50 inner."""
+    rng = np.random.default_rng(1000 * 5 + rep)
+    means = rng.uniform(-1.0, 1.0, size=(16, 16))
+    x = gmm_points(rng, n, means, 0.1)
+    y0 = gmm_points(rng, m, means, 0.1)
+    y = rotated_copy(rng, y0, 0.0, translate=True)
+    a = rng.dirichlet(np.ones(n))
+    b = rng.dirichlet(np.ones(m))
+    return Problem(x, a, y, b, 0.01, 0.01, 20, 50, "power", 1.0, lifted_dim,
+                   f"grad-{n}x{m}-d16")
+
+
+def subsample(prob: Problem, k_src: int, k_tgt: int, seed: int) -> Problem:
+    """Seeded subsample of both clouds; weights renormalised to sum 1."""
+    rng = np.random.default_rng(seed)
+    i = np.sort(rng.choice(prob.n, size=min(k_src, prob.n), replace=False))
+    j = np.sort(rng.choice(prob.m, size=min(k_tgt, prob.m), replace=False))
+    a = prob.a[i] / prob.a[i].sum()
+    b = prob.b[j] / prob.b[j].sum()
+    return Problem(prob.x[i], a, prob.y[j], b, prob.eps_start, prob.eps_end,
+                   prob.n_outer, prob.n_inner, prob.penalty, prob.p,
+                   prob.lifted_dim, prob.name + f"-sub{len(i)}x{len(j)}",
+                   {"rows": i, "cols": j})
