@@ -1,0 +1,236 @@
+/*
+ * gw.h - C ABI of the MI355X (gfx950) CNT-GW hot-path library (libgwmi.so).
+ *
+ * Problem (Section 5, "Notations"): two discrete measures
+ *   alpha = sum_i a_i delta_{x_i}  (N points in R^dx),
+ *   beta  = sum_j b_j delta_{y_j}  (M points in R^dy),
+ * positive weights summing to 1, a distortion penalty per side that is
+ * conditionally of negative type (Section 2, "Embeddable Costs"), and a
+ * temperature eps.  The library lifts both sides into centred features
+ * X (N x D), Y (M x E) (Section 3, Definition of GW-embeddings; Section 5,
+ * "CNT Embeddings") and runs Algorithm 1 (CNT-GW): per outer step the
+ * squared-norm EOT problem between [X_i, |X_i|^2/2] and [Gamma Y_j, |Y_j|^2/2]
+ * at temperature eps/8 is solved by log-domain Sinkhorn (Algorithm 3, or
+ * Algorithm 2), then Gamma <- sum_ij pi_ij X_i Y_j^T.  The N x M cost and
+ * coupling are never stored.
+ *
+ * Conventions for every entry point below:
+ *   - Array arguments named x, y, a, b, f, g, gamma, gamma0, grad_* and
+ *     features are DEVICE pointers (HIP global memory of the context's
+ *     device), float32, row-major, owned by the caller.  The library never
+ *     frees them and never keeps them after the call returns (the serving
+ *     API is the exception and says so).
+ *   - All GPU work is ordered on the context's HIP stream.  gw_solve and
+ *     gw_loss_and_grad block until their scalar results are on the host.
+ *   - Errors are returned as gw_status; nothing aborts or throws across the
+ *     ABI.  gw_last_error() gives a message for the last failing call on the
+ *     context.  On error, output buffers may hold partial results.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef GWMI_GW_H
+#define GWMI_GW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gw_ctx gw_ctx;
+typedef struct gw_server gw_server;
+
+typedef enum {
+    GW_OK = 0,
+    GW_EINVAL = 1,        /* invalid argument (sizes, weights, eps, NULL) */
+    GW_ENOMEM = 2,        /* device allocation or workspace limit */
+    GW_EDEVICE = 3,       /* HIP runtime error */
+    GW_ENUMERIC = 4,      /* non-finite value detected in the iteration */
+    GW_ESTATE = 5,        /* call not valid in the context's current state */
+    GW_EUNSUPPORTED = 6,  /* valid request this build does not implement */
+    GW_EBUSY = 7,         /* serving: result not ready yet */
+    GW_ECANCELLED = 8     /* serving: request was cancelled */
+} gw_status;
+
+/* Distortion penalty of one side (Section 2, "Embeddable Costs"). */
+typedef enum {
+    /* c(x, x') = |x - x'|^2: features are the centred points, D = dx
+       (Section 3, "Example").  */
+    GW_PEN_SQEUCLID = 0,
+    /* c(x, x') = |x - x'|^p, 0 < p < 2: landmark kernel PCA (Algorithm 4 and
+       the Kernel PCA paragraph of Appendix B.2) with the Nystrom map of
+       Algorithm 13 for every point, re-centred with the weights; D =
+       lifted_dim.  Landmarks are fitted on the first solve after
+       gw_set_penalty and stay frozen until the next gw_set_penalty. */
+    GW_PEN_POWER = 1,
+    /* the caller passes features directly (x is N x D); they are re-centred
+       with the weights, as Section 5 requires. */
+    GW_PEN_FEATURES = 2
+} gw_penalty;
+
+/* Arithmetic of the feature contraction X_i . Z_j in the Sinkhorn and
+   covariance passes.  Log-sum-exp, potentials and marginals are FP32 in
+   every form; the final marginal check is FP64. */
+typedef enum {
+    GW_FP32 = 0,    /* FP32: MFMA f32 for D >= 16, VALU for D < 16 */
+    GW_BF16 = 1,    /* BF16 x BF16 -> FP32 MFMA (D >= 16; D < 16 runs FP32) */
+    GW_BF16X3 = 2   /* split BF16 (hi*hi + hi*lo + lo*hi) on MFMA */
+} gw_precision;
+
+typedef enum {
+    GW_MODE_AUTO = 0,        /* device-side choice per iteration */
+    GW_MODE_SAFE = 1,        /* max-shifted row and column log-sum-exp */
+    GW_MODE_STABILISED = 2   /* one exponential per entry feeds both sums */
+} gw_mode;
+
+typedef struct {
+    double eps_start;          /* temperature of outer step 0, > 0 */
+    double eps_end;            /* of the last outer step; geometric in between */
+    int32_t n_outer;           /* outer CNT-GW steps, >= 1 */
+    int32_t n_inner;           /* Sinkhorn iterations per outer step, >= 1 */
+    int32_t symmetric;         /* 1: Algorithm 3 (default), 0: Algorithm 2 */
+    int32_t precision;         /* gw_precision */
+    int32_t mode;              /* gw_mode */
+    int32_t use_init_potentials; /* 1: read result->f, result->g as warm start */
+    double tol_gamma;          /* > 0: stop when |Gamma_t - Gamma_{t+1}|_F <= tol
+                                  (Algorithm 1's loop condition; one 8-byte
+                                  readback per outer step) */
+} gw_params;
+
+typedef struct {
+    /* caller-allocated device outputs (in/out for warm starts) */
+    float* f;                  /* N, Algorithm 1 convention, cost units */
+    float* g;                  /* M */
+    float* gamma;              /* D x E row-major: Gamma_T */
+    /* host scalars written by the library */
+    double loss_lift;          /* Lemma C.1 lifted GW loss of the final coupling */
+    double egw_objective;      /* loss_lift + eps_T * KL */
+    double kl;                 /* KL(pi | a x b) of the final coupling (FP64) */
+    double marginal_err;       /* Err(pi) = |pi 1 - a|_1 + |pi^T 1 - b|_1, FP64 */
+    double constant_c;         /* C(alpha, beta) of Lemma C.1 (FP64 moments) */
+    double sum_pi_nm;          /* sum_ij pi_ij |X_i|^2 |Y_j|^2 */
+    double gamma_step;         /* |Gamma_T - Gamma_{T-1}|_F */
+    double eps_final;          /* eps_T */
+    int32_t outer_done;        /* outer steps run */
+    int32_t dim_x;             /* D, lifted source dimension */
+    int32_t dim_y;             /* E */
+    int32_t safe_iters;        /* Sinkhorn iterations that ran max-shifted */
+} gw_result;
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+   (a hipStream_t; NULL = the null stream).  workspace_limit_bytes bounds the
+   library's own device memory (0 = no limit).  *out is set on success. */
+gw_status gw_create(gw_ctx** out, int device, void* hip_stream,
+                    size_t workspace_limit_bytes);
+
+/* Select the penalty of a side (0 source, 1 target, 2 both).  p is the
+   exponent for GW_PEN_POWER (0 < p < 2); lifted_dim is D (resp. E) for
+   GW_PEN_POWER (1..256); n_landmarks (>= lifted_dim + 1) and seed choose the
+   landmark subset as the first n_landmarks entries of a seeded permutation
+   (SplitMix64-driven Fisher-Yates, fixed by the library).  Clears fitted
+   landmarks of that side. */
+gw_status gw_set_penalty(gw_ctx* ctx, int side, int kind, double p,
+                         int lifted_dim, int n_landmarks, uint64_t seed);
+
+/* Use explicit landmark indices (host array of n_landmarks distinct indices
+   into the next solve's points of that side) instead of the seeded choice.
+   For GW_PEN_POWER only; clears fitted landmarks of that side. */
+gw_status gw_set_landmarks(gw_ctx* ctx, int side, const int64_t* idx_host,
+                           int n_landmarks);
+
+/* Lift one side into centred features (the setup step of Algorithm 1's
+   inputs, Eq. embedding_X / embedding_Y): features (n x D, device, caller
+   allocated; D from gw_feature_dim).  Fits landmarks if needed. */
+gw_status gw_lift(gw_ctx* ctx, int side, const float* x, int64_t n, int d,
+                  const float* w, float* features);
+
+/* Lifted dimension of a side for input dimension d under its penalty. */
+int gw_feature_dim(const gw_ctx* ctx, int side, int d);
+
+/* Solve the entropic GW problem with Algorithm 1.  gamma0 (D x E, device)
+   initialises Gamma (NULL: Gamma_0 = 0, the product coupling).  Potentials
+   start at 0 unless params->use_init_potentials.  Inputs: x (n x dx), a (n),
+   y (m x dy), b (m).  Errors: GW_EINVAL for n or m < 1, dims out of range,
+   non-finite inputs, weights <= 0 or |sum - 1| > 1e-5, eps <= 0, counts < 1;
+   GW_ENUMERIC if the iteration produced non-finite values. */
+gw_status gw_solve(gw_ctx* ctx,
+                   const float* x, int64_t n, int dx, const float* a,
+                   const float* y, int64_t m, int dy, const float* b,
+                   const gw_params* params, const float* gamma0,
+                   gw_result* out);
+
+/* Solve, then the envelope gradient of GW_eps (Appendix B.6, "EGW Gradient
+   Computations"; Algorithm 12 through the frozen Nystrom map of Algorithm 13
+   for GW_PEN_POWER) with respect to the positions and weights.  Any grad_*
+   may be NULL.  grad_x: n x dx, grad_a: n (projected so sum_i a_i g_i = 0),
+   grad_y: m x dy, grad_b: m.  The loss is out->egw_objective. */
+gw_status gw_loss_and_grad(gw_ctx* ctx,
+                           const float* x, int64_t n, int dx, const float* a,
+                           const float* y, int64_t m, int dy, const float* b,
+                           const gw_params* params, const float* gamma0,
+                           gw_result* out,
+                           float* grad_x, float* grad_a,
+                           float* grad_y, float* grad_b);
+
+/* Free the context and its device memory; waits for queued work.
+   NULL-safe. */
+void gw_destroy(gw_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char* gw_last_error(const gw_ctx* ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of independent solves on one GPU.         */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    const float* x; int64_t n; int32_t dx; const float* a;   /* device */
+    const float* y; int64_t m; int32_t dy; const float* b;   /* device */
+    gw_params params;
+    int32_t penalty;           /* gw_penalty, both sides */
+    double p;                  /* exponent for GW_PEN_POWER */
+    int32_t lifted_dim;        /* D = E for GW_PEN_POWER */
+    int32_t n_landmarks;
+    uint64_t seed;
+    float* f; float* g; float* gamma;  /* device outputs, caller allocated */
+} gw_request;
+
+typedef struct {
+    uint64_t submitted, completed, cancelled, rejected;
+    int32_t active, queued;
+    double busy_seconds;       /* wall time with at least one active request */
+} gw_server_stats;
+
+/* Create a server on ctx's device and stream.  max_slots bounds the number
+   of requests resident on the GPU at once; hbm_budget_bytes bounds their
+   total footprint (0 = no bound).  The server runs its own host thread. */
+gw_status gw_server_create(gw_ctx* ctx, int max_slots, size_t hbm_budget_bytes,
+                           gw_server** out);
+
+/* Queue a request.  The caller keeps every array of *req alive and
+   unmodified until the request completes or is cancelled.  A request whose
+   footprint alone exceeds the budget is rejected with GW_ENOMEM. */
+gw_status gw_server_submit(gw_server* s, const gw_request* req, uint64_t* ticket);
+
+/* GW_OK with *out filled when done; GW_EBUSY while queued or running;
+   GW_ECANCELLED; GW_EINVAL for an unknown ticket.  latency_s (may be NULL)
+   receives submit-to-completion wall time. */
+gw_status gw_server_poll(gw_server* s, uint64_t ticket, gw_result* out,
+                         double* latency_s);
+
+/* Block until the ticket completes (or is cancelled). */
+gw_status gw_server_wait(gw_server* s, uint64_t ticket, gw_result* out,
+                         double* latency_s);
+
+/* Cancel a queued or running request; its outputs are unspecified. */
+gw_status gw_server_cancel(gw_server* s, uint64_t ticket);
+
+gw_status gw_server_get_stats(gw_server* s, gw_server_stats* out);
+
+/* Stop the server thread (cancelling unfinished requests) and free it. */
+void gw_server_destroy(gw_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWMI_GW_H */

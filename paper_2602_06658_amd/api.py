@@ -1,0 +1,157 @@
+"""Thin Python binding over include/gw.h: argument marshalling only.
+
+PyTorch provides device memory and the HIP stream; every step of the solve
+runs in libgwmi.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp32": L.FP32, "bf16": L.BF16, "bf16x3": L.BF16X3}
+_MODE = {"auto": L.MODE_AUTO, "safe": L.MODE_SAFE, "stabilised": L.MODE_STABILISED}
+_PEN = {"sqeuclid": L.PEN_SQEUCLID, "power": L.PEN_POWER, "features": L.PEN_FEATURES}
+
+
+def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True, precision="fp32",
+                mode="auto", use_init_potentials=False, tol_gamma=0.0) -> L.GwParams:
+    p = L.GwParams()
+    p.eps_start = float(eps_start)
+    p.eps_end = float(eps_start if eps_end is None else eps_end)
+    p.n_outer = int(n_outer)
+    p.n_inner = int(n_inner)
+    p.symmetric = 1 if symmetric else 0
+    p.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    p.mode = _MODE[mode] if isinstance(mode, str) else int(mode)
+    p.use_init_potentials = 1 if use_init_potentials else 0
+    p.tol_gamma = float(tol_gamma)
+    return p
+
+
+def _result_dict(r: L.GwResult, f, g, gamma) -> dict:
+    return {
+        "f": f, "g": g, "gamma": gamma,
+        "loss_lift": r.loss_lift, "egw_objective": r.egw_objective, "kl": r.kl,
+        "marginal_err": r.marginal_err, "constant_c": r.constant_c, "sum_pi_nm": r.sum_pi_nm,
+        "gamma_step": r.gamma_step, "eps_final": r.eps_final, "outer_done": r.outer_done,
+        "dim_x": r.dim_x, "dim_y": r.dim_y, "safe_iters": r.safe_iters,
+    }
+
+
+class Context:
+    """Owns a gw_ctx on one device, ordered on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, workspace_limit: int = 0):
+        self.lib = L.load()
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        h = ctypes.c_void_p()
+        rc = self.lib.gw_create(ctypes.byref(h), device, ctypes.c_void_p(s.cuda_stream), workspace_limit)
+        if rc != L.GW_OK:
+            raise L.GWError(rc, "gw_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != L.GW_OK:
+            raise L.GWError(rc, self.lib.gw_last_error(self.h).decode())
+
+    def set_penalty(self, side: int, kind="sqeuclid", p: float = 1.0, lifted_dim: int = 0,
+                    n_landmarks: int = 0, seed: int = 0):
+        k = _PEN[kind] if isinstance(kind, str) else int(kind)
+        self._check(self.lib.gw_set_penalty(self.h, side, k, float(p), int(lifted_dim), int(n_landmarks),
+                                            ctypes.c_uint64(seed)))
+
+    def set_landmarks(self, side: int, idx):
+        arr = (ctypes.c_int64 * len(idx))(*[int(v) for v in idx])
+        self._check(self.lib.gw_set_landmarks(self.h, side, arr, len(idx)))
+
+    def feature_dim(self, side: int, d: int) -> int:
+        return self.lib.gw_feature_dim(self.h, side, d)
+
+    def lift(self, side: int, x: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+        x = _dev_f32(x, "x")
+        w = _dev_f32(w, "w")
+        n, d = x.shape
+        D = self.feature_dim(side, d)
+        out = torch.empty((n, D), dtype=torch.float32, device=x.device)
+        self._check(self.lib.gw_lift(self.h, side, _ptr(x), n, d, _ptr(w), _ptr(out)))
+        return out
+
+    def _prep(self, x, a, y, b):
+        x = _dev_f32(x, "x")
+        a = _dev_f32(a, "a")
+        y = _dev_f32(y, "y")
+        b = _dev_f32(b, "b")
+        if x.dim() != 2 or y.dim() != 2 or a.shape != (x.shape[0],) or b.shape != (y.shape[0],):
+            raise ValueError("x: (N, dx), a: (N,), y: (M, dy), b: (M,)")
+        return x, a, y, b
+
+    def solve(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
+              precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, tol_gamma=0.0) -> dict:
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        D, E = self.feature_dim(0, dx), self.feature_dim(1, dy)
+        f = torch.empty(n, dtype=torch.float32, device=x.device) if f0 is None else _dev_f32(f0, "f0").clone()
+        g = torch.empty(m, dtype=torch.float32, device=x.device) if g0 is None else _dev_f32(g0, "g0").clone()
+        gamma = torch.empty((D, E), dtype=torch.float32, device=x.device)
+        g0t = None if gamma0 is None else _dev_f32(gamma0, "gamma0")
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode,
+                          f0 is not None and g0 is not None, tol_gamma)
+        r = L.GwResult()
+        r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
+        self._check(self.lib.gw_solve(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
+                                      ctypes.byref(prm), _ptr(g0t), ctypes.byref(r)))
+        return _result_dict(r, f, g, gamma)
+
+    def loss_and_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
+                      precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, want=("x", "a", "y", "b")):
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        D, E = self.feature_dim(0, dx), self.feature_dim(1, dy)
+        f = torch.empty(n, dtype=torch.float32, device=x.device) if f0 is None else _dev_f32(f0, "f0").clone()
+        g = torch.empty(m, dtype=torch.float32, device=x.device) if g0 is None else _dev_f32(g0, "g0").clone()
+        gamma = torch.empty((D, E), dtype=torch.float32, device=x.device)
+        gx = torch.empty_like(x) if "x" in want else None
+        ga = torch.empty_like(a) if "a" in want else None
+        gy = torch.empty_like(y) if "y" in want else None
+        gb = torch.empty_like(b) if "b" in want else None
+        g0t = None if gamma0 is None else _dev_f32(gamma0, "gamma0")
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode,
+                          f0 is not None and g0 is not None, 0.0)
+        r = L.GwResult()
+        r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
+        self._check(self.lib.gw_loss_and_grad(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
+                                              ctypes.byref(prm), _ptr(g0t), ctypes.byref(r),
+                                              _ptr(gx), _ptr(ga), _ptr(gy), _ptr(gb)))
+        out = _result_dict(r, f, g, gamma)
+        out.update({"grad_x": gx, "grad_a": ga, "grad_y": gy, "grad_b": gb})
+        return out

@@ -1,0 +1,161 @@
+// extern "C" entry points of libgwmi.so (declared in include/gw.h).
+#include <cstring>
+#include <new>
+
+#include "runtime.h"
+
+using gwr::Ctx;
+using gwr::Status;
+
+struct gw_ctx {
+    Ctx c;
+};
+
+static gw_status ret(gw_ctx* ctx, const Status& s) {
+    if (ctx) ctx->c.err = s.good() ? std::string() : s.msg;
+    return s.code;
+}
+
+extern "C" {
+
+gw_status gw_create(gw_ctx** out, int device, void* hip_stream, size_t workspace_limit_bytes) {
+    if (!out) return GW_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GW_EDEVICE;
+    if (device < 0 || device >= ndev) return GW_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return GW_EDEVICE;
+    gw_ctx* ctx = new (std::nothrow) gw_ctx();
+    if (!ctx) return GW_ENOMEM;
+    ctx->c.device = device;
+    ctx->c.stream = (hipStream_t)hip_stream;
+    ctx->c.ws.set_limit(workspace_limit_bytes);
+    *out = ctx;
+    return GW_OK;
+}
+
+gw_status gw_set_penalty(gw_ctx* ctx, int side, int kind, double p, int lifted_dim, int n_landmarks, uint64_t seed) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (side < 0 || side > 2) return ret(ctx, gwr::fail(GW_EINVAL, "side must be 0, 1 or 2"));
+    if (kind < GW_PEN_SQEUCLID || kind > GW_PEN_FEATURES) return ret(ctx, gwr::fail(GW_EINVAL, "unknown penalty"));
+    if (kind == GW_PEN_POWER) {
+        if (!(p > 0.0 && p < 2.0)) return ret(ctx, gwr::fail(GW_EINVAL, "power penalty needs 0 < p < 2"));
+        if (lifted_dim < 1 || lifted_dim > gwl::MAX_DIM)
+            return ret(ctx, gwr::fail(GW_EINVAL, "lifted_dim must be in [1, 256]"));
+        if (n_landmarks < lifted_dim + 1) return ret(ctx, gwr::fail(GW_EINVAL, "need n_landmarks > lifted_dim"));
+    }
+    for (int s = 0; s < 2; ++s) {
+        if (side != 2 && side != s) continue;
+        gwr::SideCfg& c = ctx->c.side[s];
+        c.kind = kind;
+        c.p = kind == GW_PEN_POWER ? p : 2.0;
+        c.lifted_dim = kind == GW_PEN_POWER ? lifted_dim : 0;
+        c.n_landmarks = n_landmarks;
+        c.seed = seed;
+        c.explicit_idx.clear();
+        c.lm.fitted = false;
+    }
+    return ret(ctx, Status::ok());
+}
+
+gw_status gw_set_landmarks(gw_ctx* ctx, int side, const int64_t* idx_host, int n_landmarks) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (side < 0 || side > 2 || !idx_host || n_landmarks < 2) return ret(ctx, gwr::fail(GW_EINVAL, "bad landmarks"));
+    for (int s = 0; s < 2; ++s) {
+        if (side != 2 && side != s) continue;
+        gwr::SideCfg& c = ctx->c.side[s];
+        if (c.kind != GW_PEN_POWER) return ret(ctx, gwr::fail(GW_ESTATE, "landmarks need GW_PEN_POWER"));
+        if (n_landmarks < c.lifted_dim + 1) return ret(ctx, gwr::fail(GW_EINVAL, "need n_landmarks > lifted_dim"));
+        c.explicit_idx.assign(idx_host, idx_host + n_landmarks);
+        c.n_landmarks = n_landmarks;
+        c.lm.fitted = false;
+    }
+    return ret(ctx, Status::ok());
+}
+
+int gw_feature_dim(const gw_ctx* ctx, int side, int d) {
+    if (!ctx || side < 0 || side > 1) return -1;
+    return gwr::feature_dim(ctx->c.side[side], d);
+}
+
+gw_status gw_lift(gw_ctx* ctx, int side, const float* x, int64_t n, int d, const float* w, float* features) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (side < 0 || side > 1 || !x || !w || !features || n < 1 || d < 1 || d > gwl::MAX_DIM)
+        return ret(ctx, gwr::fail(GW_EINVAL, "bad lift arguments"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    const int D = gwr::feature_dim(ctx->c.side[side], d);
+    const int64_t n_pad = (n + 31) / 32 * 32;
+    Status st;
+    float* X = ctx->c.ws.get_t<float>("lift.X", (size_t)n_pad * D, &st);
+    if (!st.good()) return ret(ctx, st);
+    st = gwr::lift_side(ctx->c, side, x, n, d, w, X, n_pad, "lift.");
+    if (!st.good()) return ret(ctx, st);
+    if (hipMemcpyAsync(features, X, (size_t)n * D * sizeof(float), hipMemcpyDeviceToDevice, ctx->c.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->c.stream) != hipSuccess)
+        return ret(ctx, gwr::fail(GW_EDEVICE, "copy of lifted features"));
+    return ret(ctx, Status::ok());
+}
+
+static gw_status solve_impl(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
+                            int dy, const float* b, const gw_params* params, const float* gamma0, gw_result* out,
+                            float* grad_x, float* grad_a, float* grad_y, float* grad_b, bool want_grad) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (!out) return ret(ctx, gwr::fail(GW_EINVAL, "result is NULL"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = gwr::validate_inputs(ctx->c, x, n, dx, a, y, m, dy, b, params, "s.");
+    if (!st.good()) return ret(ctx, st);
+    if (params->use_init_potentials && (!out->f || !out->g))
+        return ret(ctx, gwr::fail(GW_EINVAL, "warm start needs result->f and result->g"));
+    gwr::Solve solve(ctx->c, "s.");
+    const float* f0 = params->use_init_potentials ? out->f : nullptr;
+    const float* g0 = params->use_init_potentials ? out->g : nullptr;
+    st = solve.setup(x, n, dx, a, y, m, dy, b, *params, gamma0, f0, g0, ctx->c.side[0].kind, ctx->c.side[1].kind,
+                     ctx->c.stream);
+    if (!st.good()) return ret(ctx, st);
+    while (!solve.done()) {
+        st = solve.outer_step();
+        if (!st.good()) return ret(ctx, st);
+    }
+    st = solve.finish(out);
+    if (!st.good()) return ret(ctx, st);
+    if (want_grad) {
+        st = solve.gradients(grad_x, grad_a, grad_y, grad_b);
+        if (!st.good()) return ret(ctx, st);
+    }
+    return ret(ctx, Status::ok());
+}
+
+gw_status gw_solve(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
+                   const float* b, const gw_params* params, const float* gamma0, gw_result* out) {
+    return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, nullptr, nullptr, nullptr, nullptr, false);
+}
+
+gw_status gw_loss_and_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
+                           int dy, const float* b, const gw_params* params, const float* gamma0, gw_result* out,
+                           float* grad_x, float* grad_a, float* grad_y, float* grad_b) {
+    return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, grad_x, grad_a, grad_y, grad_b, true);
+}
+
+void gw_destroy(gw_ctx* ctx) {
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->c.mu);
+        (void)hipSetDevice(ctx->c.device);
+        (void)hipStreamSynchronize(ctx->c.stream);
+        gwr::release_landmarks(ctx->c);
+        ctx->c.ws.release_all();
+    }
+    delete ctx;
+}
+
+const char* gw_last_error(const gw_ctx* ctx) {
+    if (!ctx) return "NULL context";
+    return ctx->c.err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// MFMA tile cores, LDS chunk staging and the mode gate shared by the pass,
+// covariance and gradient kernels.
+#pragma once
+
+#include "gw_device.h"
+
+namespace gwk {
+
+using namespace gwl;
+
+// ---------------------------------------------------------------------------
+// MFMA cores: a 32x32 tile of s from packed operands.
+// ---------------------------------------------------------------------------
+
+template <int KS>
+struct CoreBF16 {
+    static constexpr int UNITS = KS;  // 16-byte units per lane per chunk
+    struct A {
+        bf16x8_t v[KS];
+    };
+    __device__ static void load(A& a, const uint4* pack, int chunk, int lane) {
+        const uint4* p = pack + (size_t)chunk * KS * 64 + lane;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a.v[s] = __builtin_bit_cast(bf16x8_t, p[s * 64]);
+    }
+    // s = X Zs^T: lane l gets column l % 32, rows acc_row(q, l).
+    __device__ static f32x16_t tile(const A& a, const uint4* lds, int lane) {
+        f32x16_t acc = (f32x16_t)0.0f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[s], __builtin_bit_cast(bf16x8_t, lds[s * 64 + lane]),
+                                                          acc, 0, 0, 0);
+        return acc;
+    }
+    // s^T = Zs X^T: lane l gets row l % 32, columns acc_row(q, l).
+    __device__ static f32x16_t tileT(const A& a, const uint4* lds, int lane) {
+        f32x16_t acc = (f32x16_t)0.0f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, lds[s * 64 + lane]), a.v[s],
+                                                          acc, 0, 0, 0);
+        return acc;
+    }
+};
+
+template <int KG>
+struct CoreF32 {
+    static constexpr int UNITS = KG;  // groups of four 32x32x2 slabs
+    struct A {
+        f32x4_t v[KG];
+    };
+    __device__ static void load(A& a, const uint4* pack, int chunk, int lane) {
+        const uint4* p = pack + (size_t)chunk * KG * 64 + lane;
+#pragma unroll
+        for (int g = 0; g < KG; ++g) a.v[g] = __builtin_bit_cast(f32x4_t, p[g * 64]);
+    }
+    __device__ static f32x16_t tile(const A& a, const uint4* lds, int lane) {
+        f32x16_t acc = (f32x16_t)0.0f;
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            f32x4_t b = __builtin_bit_cast(f32x4_t, lds[g * 64 + lane]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[g][e], b[e], acc, 0, 0, 0);
+        }
+        return acc;
+    }
+    __device__ static f32x16_t tileT(const A& a, const uint4* lds, int lane) {
+        f32x16_t acc = (f32x16_t)0.0f;
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            f32x4_t b = __builtin_bit_cast(f32x4_t, lds[g * 64 + lane]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b[e], a.v[g][e], acc, 0, 0, 0);
+        }
+        return acc;
+    }
+};
+
+__device__ __forceinline__ bool should_run(const int* ctl, int run_if) {
+    if (run_if == RUN_ALWAYS) return true;
+    const int mode = ctl[CTL_MODE];
+    if (run_if == RUN_STAB) return mode == MODE_STAB;
+    if (run_if == RUN_SAFE) return mode == MODE_SAFE;
+    return mode == MODE_STAB && ctl[CTL_BAD] != 0;  // RUN_RETRY
+}
+
+// Cooperative copy of one 32-column chunk of the B pack into LDS, staged
+// through registers so the load of chunk c+1 overlaps the compute of c.
+template <int NU>
+struct ChunkStage {
+    static constexpr int PER = (NU + THREADS - 1) / THREADS;
+    uint4 r[PER];
+    __device__ void load(const uint4* src, int tid) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            int u = tid + k * THREADS;
+            if (u < NU) r[k] = src[u];
+        }
+    }
+    __device__ void store(uint4* dst, int tid) const {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            int u = tid + k * THREADS;
+            if (u < NU) dst[u] = r[k];
+        }
+    }
+};
+
+}  // namespace gwk

@@ -1,0 +1,661 @@
+// Covariance pass of Algorithm 1 (X~_j and Gamma_{t+1} = sum_j b_j X~_j Y_j^T,
+// i.e. Gamma_{t+1} = sum_ij pi_ij X_i Y_j^T), computed row-wise as
+// T_i = sum_j pi_ij Y_j, then Gamma = sum_i X_i T_i^T in FP64; the same pass
+// gives r_i = sum_j pi_ij and rm_i = sum_j pi_ij |Y_j|^2 for the lifted loss
+// of Lemma C.1 (sum pi |x|^2 |y|^2 = sum_i |X_i|^2 rm_i).  With the operands
+// swapped it gives the column-side sums the target gradient needs.
+//
+// Also: the FP64 evaluation of the final coupling for Err(pi) (Appendix A.1)
+// and KL(pi | a x b).
+#include "gw_cores.h"
+#include "gw_prep.h"
+
+using namespace gwl;
+
+namespace gwk {
+
+struct CovArgs {
+    const uint4* A;     // row-side pack
+    const uint4* B;     // column-side pack
+    const float* W;     // column-side features, m_pad x dw
+    const float* mw;    // column-side norms
+    int dw;
+    float* Tp;
+    float* rp;
+    float* rmp;
+    int tw;
+    int n_chunks_r, n_chunks_c, rg, bc_chunks, n_mt_r, n_mt_c, n_pad, m_pad;
+};
+
+// lane = row (within a 32-row tile); tileT gives s^T so that lane l holds
+// pi[i = l%32][j = acc_row(q, l)].  T accumulates with v_mfma_f32_32x32x2f32:
+// D[e][i] += sum_{k=h} W[j(q,h)][e] pi[i][j(q,h)].
+template <class C, int RW, int ES>
+__global__ void __launch_bounds__(THREADS) k_cov_mfma(CovArgs p) {
+    constexpr int NU = C::UNITS * 64;
+    constexpr int WS = ES * 32 + 1;  // LDS row stride of the W chunk
+    __shared__ uint4 zbuf[2][NU];
+    __shared__ float wbuf[2][32 * WS];
+    __shared__ float mbuf[2][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
+    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    const int c0 = cb * p.bc_chunks;
+    const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
+
+    auto load_w = [&](int buf, int c) {
+        for (int u = tid; u < 32 * ES * 32; u += THREADS) {
+            const int j = u / (ES * 32), e = u - j * (ES * 32);
+            const int col = c * 32 + j;
+            wbuf[buf][j * WS + e] = e < p.dw ? p.W[(size_t)col * p.dw + e] : 0.f;
+        }
+        if (tid < 32) mbuf[buf][tid] = p.mw[c * 32 + tid];
+    };
+    ChunkStage<NU> st;
+    st.load(p.B + (size_t)c0 * NU, tid);
+    st.store(zbuf[0], tid);
+    load_w(0, c0);
+    __syncthreads();
+
+    typename C::A a[RW];
+    f32x16_t tacc[RW][ES];
+    float r[RW], rm[RW];
+    bool act[RW];
+    int rchunk0 = 0;
+    const int total = p.rg * nch;
+    for (int it = 0; it < total; ++it) {
+        const int g = it / nch, cc = it - g * nch;
+        if (cc == 0) {
+            rchunk0 = (rb * p.rg + g) * (WAVES * RW) + wave * RW;
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                act[t] = rchunk0 + t < p.n_chunks_r;
+                if (act[t]) C::load(a[t], p.A, rchunk0 + t, lane);
+#pragma unroll
+                for (int es = 0; es < ES; ++es) tacc[t][es] = (f32x16_t)0.0f;
+                r[t] = 0.f;
+                rm[t] = 0.f;
+            }
+        }
+        const bool has_next = it + 1 < total;
+        const int cn = c0 + (it + 1) % nch;
+        if (has_next) st.load(p.B + (size_t)cn * NU, tid);
+        const uint4* zb = zbuf[it & 1];
+        const float* wb = wbuf[it & 1];
+        const float* mb = mbuf[it & 1];
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+            if (act[t]) {
+                f32x16_t s = C::tileT(a[t], zb, lane);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const float pq = fast_exp2(s[q]);
+                    const int jr = acc_row(q, lane);
+                    r[t] += pq;
+                    rm[t] = fmaf(pq, mb[jr], rm[t]);
+#pragma unroll
+                    for (int es = 0; es < ES; ++es)
+                        tacc[t][es] = __builtin_amdgcn_mfma_f32_32x32x2f32(wb[jr * WS + es * 32 + (lane & 31)], pq,
+                                                                           tacc[t][es], 0, 0, 0);
+                }
+            }
+        }
+        if (cc == nch - 1) {
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                if (act[t]) {
+                    const float rt = r[t] + shfl_xor_f(r[t], 32);
+                    const float rmt = rm[t] + shfl_xor_f(rm[t], 32);
+                    const int row = (rchunk0 + t) * 32 + (lane & 31);
+                    if (lane < 32) {
+                        p.rp[(size_t)cb * p.n_pad + row] = rt;
+                        p.rmp[(size_t)cb * p.n_pad + row] = rmt;
+                    }
+                    float* dst = p.Tp + ((size_t)cb * p.n_pad + row) * p.tw;
+#pragma unroll
+                    for (int es = 0; es < ES; ++es)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) dst[es * 32 + acc_row(q, lane)] = tacc[t][es][q];
+                }
+            }
+        }
+        if (has_next) {
+            st.store(zbuf[(it + 1) & 1], tid);
+            load_w((it + 1) & 1, cn);
+        }
+        __syncthreads();
+    }
+}
+
+// VALU covariance for D < 16 in the direct exponent form of the VALU pass:
+// lane = row, column records [Z (D), Vh, m/2, Vl, W (dw)] in LDS; the column
+// norm m_j doubles as the weight of rm_i.
+constexpr int CRV = 2;                      // rows per lane
+constexpr int COV_VALU_ROWS = WAVES * 64 * CRV;
+constexpr int MAX_VALU_W = 16;
+
+struct CovValuArgs {
+    const float* X;
+    const float* xn;
+    const float* U;
+    const float* Ul;
+    const float* Z;
+    const float* mm;
+    const float* V;
+    const float* Vl;
+    const float* W;
+    float kappa;
+    int dw;
+    float* Tp;
+    float* rp;
+    float* rmp;
+    int tw;
+    int n_pad, m_pad, n_chunks_c, rg, bc_chunks, n_mt_r, n_mt_c;
+};
+
+template <int D>
+__global__ void __launch_bounds__(THREADS) k_cov_valu(CovValuArgs p) {
+    const int R = D + 3 + p.dw;
+    extern __shared__ float zc[];  // [2][32 * R]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
+    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    const int c0 = cb * p.bc_chunks;
+    const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
+    auto load = [&](int buf, int c) {
+        float* dst = zc + buf * 32 * R;
+        for (int u = tid; u < 32 * R; u += THREADS) {
+            const int j = u / R, k = u - j * R;
+            const int col = c * 32 + j;
+            float v;
+            if (k < D) v = p.Z[(size_t)col * D + k];
+            else if (k == D) v = p.V[col];
+            else if (k == D + 1) v = 0.5f * p.mm[col];
+            else if (k == D + 2) v = p.Vl[col];
+            else v = p.W[(size_t)col * p.dw + (k - D - 3)];
+            dst[u] = v;
+        }
+    };
+    load(0, c0);
+    __syncthreads();
+    float xr[CRV][D], ur[CRV], ulr[CRV], nr[CRV], r[CRV], rm[CRV], T[CRV][MAX_VALU_W];
+    int row0 = 0;
+    const int total = p.rg * nch;
+    for (int it = 0; it < total; ++it) {
+        const int g = it / nch, cc = it - g * nch;
+        if (cc == 0) {
+            row0 = (rb * p.rg + g) * COV_VALU_ROWS + wave * 64 * CRV;
+#pragma unroll
+            for (int k = 0; k < CRV; ++k) {
+                const int row = row0 + k * 64 + lane;
+                const bool ok = row < p.n_pad;
+#pragma unroll
+                for (int d = 0; d < D; ++d) xr[k][d] = ok ? p.X[(size_t)row * D + d] : 0.f;
+                ur[k] = ok ? p.U[row] : -INFINITY;
+                ulr[k] = ok ? p.Ul[row] : 0.f;
+                nr[k] = ok ? 0.5f * p.xn[row] : 0.f;
+                r[k] = 0.f;
+                rm[k] = 0.f;
+#pragma unroll
+                for (int e = 0; e < MAX_VALU_W; ++e) T[k][e] = 0.f;
+            }
+        }
+        const float* zb = zc + (it & 1) * 32 * R;
+        for (int j = 0; j < 32; ++j) {
+            const float* zr = zb + j * R;
+#pragma unroll
+            for (int k = 0; k < CRV; ++k) {
+                const float dl = nr[k] - zr[D + 1];
+                float dist = dl * dl;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const float df = xr[k][d] - zr[d];
+                    dist = fmaf(df, df, dist);
+                }
+                const float e = fast_exp2(assemble_exponent(ur[k], ulr[k], zr[D], zr[D + 2], p.kappa * dist));
+                r[k] += e;
+                rm[k] = fmaf(e, 2.f * zr[D + 1], rm[k]);
+#pragma unroll
+                for (int w = 0; w < MAX_VALU_W; ++w)
+                    if (w < p.dw) T[k][w] = fmaf(e, zr[D + 3 + w], T[k][w]);
+            }
+        }
+        if (cc == nch - 1) {
+#pragma unroll
+            for (int k = 0; k < CRV; ++k) {
+                const int row = row0 + k * 64 + lane;
+                if (row < p.n_pad) {
+                    p.rp[(size_t)cb * p.n_pad + row] = r[k];
+                    p.rmp[(size_t)cb * p.n_pad + row] = rm[k];
+                    float* dst = p.Tp + ((size_t)cb * p.n_pad + row) * p.tw;
+                    for (int w = 0; w < p.dw; ++w) dst[w] = T[k][w];
+                }
+            }
+        }
+        if (it + 1 < total) load((it + 1) & 1, c0 + (it + 1) % nch);
+        __syncthreads();
+    }
+}
+
+int cov_tw(int path, int dw) { return path == 1 ? dw : (dw + 31) / 32 * 32; }
+
+int cov_rows_per_group(int path, int prec, int d, int dw) {
+    if (path == 1) return COV_VALU_ROWS;
+    const int units = pack_units(prec, d);
+    const int es = (dw + 31) / 32;
+    const int rw = (units <= 9 && es <= 4) ? 2 : 1;
+    return WAVES * rw * 32;
+}
+
+template <class C, int RW>
+static hipError_t launch_cov_mfma_es(const CovArgs& a, int es, int grid, hipStream_t stream) {
+    switch (es) {
+        case 1: hipLaunchKernelGGL((k_cov_mfma<C, RW, 1>), dim3(grid), dim3(THREADS), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((k_cov_mfma<C, RW, 2>), dim3(grid), dim3(THREADS), 0, stream, a); break;
+        case 3: hipLaunchKernelGGL((k_cov_mfma<C, RW, 3>), dim3(grid), dim3(THREADS), 0, stream, a); break;
+        case 4: hipLaunchKernelGGL((k_cov_mfma<C, RW, 4>), dim3(grid), dim3(THREADS), 0, stream, a); break;
+        case 6: hipLaunchKernelGGL((k_cov_mfma<C, 1, 6>), dim3(grid), dim3(THREADS), 0, stream, a); break;
+        case 8: hipLaunchKernelGGL((k_cov_mfma<C, 1, 8>), dim3(grid), dim3(THREADS), 0, stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, const float* X, const float* xn,
+                      const float* U, const float* Ul, const float* Zs, const float* ms, const float* V,
+                      const float* Vl, float kappa, const float* W, const float* mw, int dw, int64_t n_pad,
+                      int64_t m_pad, int rg, int bc_chunks, int n_mt_r, int n_mt_c, const CovOut& out,
+                      hipStream_t stream) {
+    const int grid = n_mt_r * n_mt_c;
+    if (path == 1) {
+        if (dw > MAX_VALU_W) return hipErrorInvalidValue;
+        CovValuArgs a;
+        a.X = X;
+        a.xn = xn;
+        a.U = U;
+        a.Ul = Ul;
+        a.Z = Zs;
+        a.mm = ms;
+        a.V = V;
+        a.Vl = Vl;
+        a.W = W;
+        a.kappa = kappa;
+        a.dw = dw;
+        a.Tp = out.Tp;
+        a.rp = out.rp;
+        a.rmp = out.rmp;
+        a.tw = out.tw;
+        a.n_pad = (int)n_pad;
+        a.m_pad = (int)m_pad;
+        a.n_chunks_c = (int)(m_pad / 32);
+        a.rg = rg;
+        a.bc_chunks = bc_chunks;
+        a.n_mt_r = n_mt_r;
+        a.n_mt_c = n_mt_c;
+        const size_t lds = 2 * 32 * (size_t)(d + 3 + dw) * sizeof(float);
+        switch (d) {
+#define GW_COV_CASE(DD)                                                                             \
+    case DD:                                                                                        \
+        hipLaunchKernelGGL((k_cov_valu<DD>), dim3(grid), dim3(THREADS), lds, stream, a); \
+        break;
+            GW_COV_CASE(1) GW_COV_CASE(2) GW_COV_CASE(3) GW_COV_CASE(4) GW_COV_CASE(5)
+            GW_COV_CASE(6) GW_COV_CASE(7) GW_COV_CASE(8) GW_COV_CASE(9) GW_COV_CASE(10)
+            GW_COV_CASE(11) GW_COV_CASE(12) GW_COV_CASE(13) GW_COV_CASE(14) GW_COV_CASE(15)
+#undef GW_COV_CASE
+            default:
+                return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    CovArgs a;
+    a.A = (const uint4*)A;
+    a.B = (const uint4*)B;
+    a.W = W;
+    a.mw = mw;
+    a.dw = dw;
+    a.Tp = out.Tp;
+    a.rp = out.rp;
+    a.rmp = out.rmp;
+    a.tw = out.tw;
+    a.n_chunks_r = (int)(n_pad / 32);
+    a.n_chunks_c = (int)(m_pad / 32);
+    a.rg = rg;
+    a.bc_chunks = bc_chunks;
+    a.n_mt_r = n_mt_r;
+    a.n_mt_c = n_mt_c;
+    a.n_pad = (int)n_pad;
+    a.m_pad = (int)m_pad;
+    const int es = out.tw / 32;
+    const int units = pack_units(prec, d);
+    if (prec == PREC_F32) {
+        switch (units) {
+            case 3: return launch_cov_mfma_es<CoreF32<3>, 2>(a, es, grid, stream);
+            case 5: return launch_cov_mfma_es<CoreF32<5>, 2>(a, es, grid, stream);
+            case 7: return launch_cov_mfma_es<CoreF32<7>, 2>(a, es, grid, stream);
+            case 9: return launch_cov_mfma_es<CoreF32<9>, 2>(a, es, grid, stream);
+            case 13: return launch_cov_mfma_es<CoreF32<13>, 1>(a, es, grid, stream);
+            case 17: return launch_cov_mfma_es<CoreF32<17>, 1>(a, es, grid, stream);
+            case 25: return launch_cov_mfma_es<CoreF32<25>, 1>(a, es, grid, stream);
+            case 33: return launch_cov_mfma_es<CoreF32<33>, 1>(a, es, grid, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (units) {
+        case 2: return launch_cov_mfma_es<CoreBF16<2>, 2>(a, es, grid, stream);
+        case 3: return launch_cov_mfma_es<CoreBF16<3>, 2>(a, es, grid, stream);
+        case 4: return launch_cov_mfma_es<CoreBF16<4>, 2>(a, es, grid, stream);
+        case 5: return launch_cov_mfma_es<CoreBF16<5>, 2>(a, es, grid, stream);
+        case 7: return launch_cov_mfma_es<CoreBF16<7>, 2>(a, es, grid, stream);
+        case 9: return launch_cov_mfma_es<CoreBF16<9>, 2>(a, es, grid, stream);
+        case 10: return launch_cov_mfma_es<CoreBF16<10>, 1>(a, es, grid, stream);
+        case 13: return launch_cov_mfma_es<CoreBF16<13>, 1>(a, es, grid, stream);
+        case 17: return launch_cov_mfma_es<CoreBF16<17>, 1>(a, es, grid, stream);
+        case 19: return launch_cov_mfma_es<CoreBF16<19>, 1>(a, es, grid, stream);
+        case 25: return launch_cov_mfma_es<CoreBF16<25>, 1>(a, es, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduction of the covariance partials (fixed order) and Gamma in FP64.
+// ---------------------------------------------------------------------------
+
+constexpr int RED_ROWS = 64;
+
+__global__ void __launch_bounds__(256) k_cov_reduce(const float* Tp, const float* rp, const float* rmp, int n_mt_c,
+                                                    int tw, int64_t n, int64_t n_pad, const float* Xs, int dx,
+                                                    const float* xs_norm, int dw, float* T, float* r, float* rm,
+                                                    double* part) {
+    extern __shared__ float tsh[];  // RED_ROWS x (dw + 1)
+    __shared__ double sred[256];
+    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
+    double acc_r = 0.0, acc_nm = 0.0;
+    for (int u = threadIdx.x; u < RED_ROWS * dw; u += blockDim.x) {
+        const int li = u / dw, e = u - li * dw;
+        const int64_t i = r0 + li;
+        float s = 0.f;
+        if (i < n)
+            for (int c = 0; c < n_mt_c; ++c) s += Tp[((size_t)c * n_pad + i) * tw + e];
+        tsh[li * (dw + 1) + e] = s;
+        if (T && i < n) T[i * dw + e] = s;
+    }
+    if (threadIdx.x < RED_ROWS) {
+        const int64_t i = r0 + threadIdx.x;
+        if (i < n) {
+            float sr = 0.f, sm = 0.f;
+            for (int c = 0; c < n_mt_c; ++c) {
+                sr += rp[(size_t)c * n_pad + i];
+                sm += rmp[(size_t)c * n_pad + i];
+            }
+            if (r) r[i] = sr;
+            if (rm) rm[i] = sm;
+            acc_r = (double)sr;
+            acc_nm = (double)sm * (double)xs_norm[i];
+        }
+    }
+    __syncthreads();
+    const int width = dx * dw;
+    double* out = part + (size_t)blockIdx.x * (width + 2);
+    for (int pidx = threadIdx.x; pidx < width; pidx += blockDim.x) {
+        const int dd = pidx / dw, e = pidx - dd * dw;
+        double s = 0.0;
+        for (int li = 0; li < RED_ROWS; ++li) {
+            const int64_t i = r0 + li;
+            if (i >= n) break;
+            s += (double)Xs[i * dx + dd] * (double)tsh[li * (dw + 1) + e];
+        }
+        out[pidx] = s;
+    }
+    // fixed-order block sums of the two scalars
+    sred[threadIdx.x] = acc_r;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sred[threadIdx.x] += sred[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[width] = sred[0];
+    __syncthreads();
+    sred[threadIdx.x] = acc_nm;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sred[threadIdx.x] += sred[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[width + 1] = sred[0];
+}
+
+size_t cov_reduce_part_doubles(int64_t n, int dx, int dw) {
+    return (size_t)((n + RED_ROWS - 1) / RED_ROWS) * (dx * dw + 2);
+}
+
+hipError_t launch_cov_reduce(const CovOut& in, int n_mt_c, int64_t n, int64_t n_pad, const float* Xs, int dx,
+                             const float* xs_norm, int dw, float* T, float* r, float* rm, double* part,
+                             hipStream_t stream) {
+    const int nblk = (int)((n + RED_ROWS - 1) / RED_ROWS);
+    const size_t lds = (size_t)RED_ROWS * (dw + 1) * sizeof(float);
+    hipLaunchKernelGGL(k_cov_reduce, dim3(nblk), dim3(256), lds, stream, in.Tp, in.rp, in.rmp, n_mt_c, in.tw, n,
+                       n_pad, Xs, dx, xs_norm, dw, T, r, rm, part);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_gamma_final(const double* part, int nblk, int dx, int dw,
+                                                     const float* gamma_old, double* gamma64, float* gamma32,
+                                                     double* scal) {
+    __shared__ double s1[256], s2[256];
+    const int width = dx * dw;
+    double a1 = 0.0, a2 = 0.0;
+    for (int pidx = threadIdx.x; pidx < width + 2; pidx += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (width + 2) + pidx];
+        if (pidx < width) {
+            gamma64[pidx] = s;
+            gamma32[pidx] = (float)s;
+            const double dlt = s - (double)gamma_old[pidx];
+            a1 += s * s;
+            a2 += dlt * dlt;
+        } else if (pidx == width) {
+            scal[0] = s;
+        } else {
+            scal[1] = s;
+        }
+    }
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s1[threadIdx.x] += s1[threadIdx.x + st];
+            s2[threadIdx.x] += s2[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scal[2] = s1[0];
+        scal[3] = s2[0];
+    }
+}
+
+hipError_t launch_gamma_final(const double* part, int64_t n, int dx, int dw, const float* gamma_old, double* gamma64,
+                              float* gamma32, double* scal, hipStream_t stream) {
+    const int nblk = (int)((n + RED_ROWS - 1) / RED_ROWS);
+    hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(256), 0, stream, part, nblk, dx, dw, gamma_old, gamma64, gamma32,
+                       scal);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 check: s_ij = sum_k A_ik B_jk evaluated exactly in FP64 from the
+// packed operands (the coupling the passes iterate), pi = 2^s.
+// Thread = row; columns staged in LDS 32 at a time; K in slabs of 16.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float pack_elem(const void* pack, int prec, int units, int row, int k) {
+    if (prec == PREC_F32) return ((const float*)pack)[f32_pack_off(row, k, units)];
+    return bf16_bits_to_f32(((const uint16_t*)pack)[bf16_pack_off(row, k, units)]);
+}
+
+__global__ void __launch_bounds__(256) k_check64(int prec, int units, int K, const void* A, const void* B, int64_t n,
+                                                 int64_t m, const float* la2, const float* lb2, double* rsum,
+                                                 double* kl) {
+    extern __shared__ float bsh[];  // 32 x (K + 1)
+    __shared__ float lbs[32];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    double rs = 0.0, klr = 0.0;
+    const double lai = act ? (double)la2[i] : 0.0;
+    const int64_t nchunks = (m + 31) / 32;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        __syncthreads();
+        for (int u = threadIdx.x; u < 32 * K; u += blockDim.x) {
+            const int j = u / K, k = u - j * K;
+            bsh[j * (K + 1) + k] = pack_elem(B, prec, units, (int)(c * 32 + j), k);
+        }
+        if (threadIdx.x < 32) lbs[threadIdx.x] = lb2 ? lb2[c * 32 + threadIdx.x] : 0.f;
+        __syncthreads();
+        if (!act) continue;
+        double acc[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            float av[16];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) av[kk] = k0 + kk < K ? pack_elem(A, prec, units, (int)i, k0 + kk) : 0.f;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const float* br = bsh + j * (K + 1) + k0;
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk)
+                    if (k0 + kk < K) acc[j] = fma((double)av[kk], (double)br[kk], acc[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            if (c * 32 + j < m) {
+                const double p = exp2(acc[j]);
+                rs += p;
+                if (kl && p > 0.0) klr += p * (acc[j] - lai - (double)lbs[j]);
+            }
+        }
+    }
+    if (act) {
+        rsum[i] = rs;
+        if (kl) kl[i] = klr * 0.6931471805599453;
+    }
+}
+
+hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols, int64_t n, int64_t n_pad, int64_t m,
+                          int64_t m_pad, const float* la2, const float* lb2, double* rsum, double* kl,
+                          hipStream_t stream) {
+    (void)n_pad;
+    (void)m_pad;
+    const int K = pack_k(prec, d);
+    const int units = pack_units(prec, d);
+    const size_t lds = (size_t)32 * (K + 1) * sizeof(float);
+    hipLaunchKernelGGL(k_check64, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, stream, prec, units, K, Arows,
+                       Bcols, n, m, la2, lb2, rsum, kl);
+    return hipGetLastError();
+}
+
+// FP64 check in the direct form of the VALU path.
+__global__ void __launch_bounds__(256) k_check64_direct(int d, const float* X, const float* xn, const float* U,
+                                                        const float* Ul, const float* Z, const float* zm,
+                                                        const float* V, const float* Vl, float kappa, int64_t n,
+                                                        int64_t m, const float* la2, const float* lb2, double* rsum,
+                                                        double* kl) {
+    extern __shared__ float rec[];  // 32 x (d + 4): Z, Vh, m, lb2, Vl
+    const int R = d + 4;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool act = i < n;
+    double xi[16];
+    for (int k = 0; k < 16; ++k) xi[k] = (act && k < d) ? (double)X[i * d + k] : 0.0;
+    const double ni = act ? (double)xn[i] : 0.0;
+    const double ui = act ? join_df(U[i], Ul[i]) : 0.0;
+    const double lai = act ? (double)la2[i] : 0.0;
+    const double kap = (double)kappa;
+    double rs = 0.0, klr = 0.0;
+    const int64_t nchunks = (m + 31) / 32;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        __syncthreads();
+        for (int u = threadIdx.x; u < 32 * R; u += blockDim.x) {
+            const int j = u / R, k = u - j * R;
+            const int64_t col = c * 32 + j;
+            float v = 0.f;
+            if (col < m) {
+                if (k < d) v = Z[col * d + k];
+                else if (k == d) v = V[col];
+                else if (k == d + 1) v = zm[col];
+                else if (k == d + 2) v = lb2 ? lb2[col] : 0.f;
+                else v = Vl[col];
+            }
+            rec[u] = v;
+        }
+        __syncthreads();
+        if (!act) continue;
+        for (int j = 0; j < 32 && c * 32 + j < m; ++j) {
+            const float* zr = rec + j * R;
+            double dist = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double df = xi[k] - (double)zr[k];
+                dist += df * df;
+            }
+            const double dl = 0.5 * (ni - (double)zr[d + 1]);
+            dist += dl * dl;
+            const double s = ui + join_df(zr[d], zr[d + 3]) - kap * dist;
+            const double p = exp2(s);
+            rs += p;
+            if (kl && p > 0.0) klr += p * (s - lai - (double)zr[d + 2]);
+        }
+    }
+    if (act) {
+        rsum[i] = rs;
+        if (kl) kl[i] = klr * 0.6931471805599453;
+    }
+}
+
+hipError_t launch_check64_direct(int d, const float* X, const float* xn, const float* U, const float* Ul,
+                                 const float* Z, const float* zm, const float* V, const float* Vl, float kappa,
+                                 int64_t n, int64_t m, const float* la2, const float* lb2, double* rsum, double* kl,
+                                 hipStream_t stream) {
+    const size_t lds = (size_t)32 * (d + 4) * sizeof(float);
+    hipLaunchKernelGGL(k_check64_direct, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, stream, d, X, xn, U, Ul,
+                       Z, zm, V, Vl, kappa, n, m, la2, lb2, rsum, kl);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_check_final(const double* r64, const double* kl, int64_t n, const float* a,
+                                                     const double* c64, int64_t m, const float* b, double asum,
+                                                     double bsum, double* scal) {
+    __shared__ double s1[256], s2[256], s3[256];
+    double e = 0.0, k = 0.0, t = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        e += fabs(r64[i] - (double)a[i] / asum);
+        k += kl[i];
+        t += r64[i];
+    }
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) e += fabs(c64[j] - (double)b[j] / bsum);
+    s1[threadIdx.x] = e;
+    s2[threadIdx.x] = k;
+    s3[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s1[threadIdx.x] += s1[threadIdx.x + st];
+            s2[threadIdx.x] += s2[threadIdx.x + st];
+            s3[threadIdx.x] += s3[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scal[4] = s1[0];
+        scal[5] = s2[0];
+        scal[6] = s3[0];
+    }
+}
+
+hipError_t launch_check_final(const double* r64, const double* kl, int64_t n, const float* a, const double* c64,
+                              int64_t m, const float* b, double asum, double bsum, double* scal, hipStream_t stream) {
+    hipLaunchKernelGGL(k_check_final, dim3(1), dim3(256), 0, stream, r64, kl, n, a, c64, m, b, asum, bsum, scal);
+    return hipGetLastError();
+}
+
+}  // namespace gwk

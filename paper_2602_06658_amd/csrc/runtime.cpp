@@ -1,0 +1,508 @@
+// Host runtime: workspace, validation, lifting dispatch and the Algorithm 1
+// state machine (Section 5).  All device work is ordered on one HIP stream;
+// the host blocks only at validation and at the final scalar readback (and
+// once per outer step when a Gamma tolerance is set).
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace gwr {
+
+using namespace gwl;
+
+Status fail(gw_status c, const std::string& m) {
+    Status s;
+    s.code = c;
+    s.msg = m;
+    return s;
+}
+
+Status hip_fail(hipError_t e, const char* where) {
+    return fail(e == hipErrorOutOfMemory ? GW_ENOMEM : GW_EDEVICE,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Workspace
+// ---------------------------------------------------------------------------
+
+Workspace::~Workspace() { release_all(); }
+
+void* Workspace::get(const std::string& name, size_t bytes, Status* st) {
+    if (bytes == 0) bytes = 16;
+    auto it = bufs_.find(name);
+    if (it != bufs_.end() && it->second.bytes >= bytes) return it->second.p;
+    size_t old = 0;
+    if (it != bufs_.end()) old = it->second.bytes;
+    if (limit_ && total_ - old + bytes > limit_) {
+        *st = fail(GW_ENOMEM, "workspace limit exceeded allocating '" + name + "' (" + std::to_string(bytes) +
+                                  " bytes, in use " + std::to_string(total_) + ", limit " + std::to_string(limit_) +
+                                  ")");
+        return nullptr;
+    }
+    if (it != bufs_.end()) {
+        (void)hipFree(it->second.p);
+        total_ -= it->second.bytes;
+        bufs_.erase(it);
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        *st = hip_fail(e, ("hipMalloc " + name).c_str());
+        return nullptr;
+    }
+    bufs_[name] = Buf{p, bytes};
+    total_ += bytes;
+    return p;
+}
+
+void Workspace::release_all() {
+    for (auto& kv : bufs_) (void)hipFree(kv.second.p);
+    bufs_.clear();
+    total_ = 0;
+}
+
+void Workspace::release_prefix(const std::string& prefix) {
+    for (auto it = bufs_.begin(); it != bufs_.end();) {
+        if (it->first.compare(0, prefix.size(), prefix) == 0) {
+            (void)hipFree(it->second.p);
+            total_ -= it->second.bytes;
+            it = bufs_.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+
+int feature_dim(const SideCfg& s, int d) {
+    if (s.kind == GW_PEN_POWER) return s.lifted_dim;
+    return d;
+}
+
+static Status check_params(const gw_params* prm) {
+    if (!prm) return fail(GW_EINVAL, "params is NULL");
+    if (!(prm->eps_start > 0.0) || !(prm->eps_end > 0.0) || !std::isfinite(prm->eps_start) ||
+        !std::isfinite(prm->eps_end))
+        return fail(GW_EINVAL, "eps must be finite and > 0");
+    if (prm->n_outer < 1 || prm->n_inner < 1) return fail(GW_EINVAL, "n_outer and n_inner must be >= 1");
+    if (prm->precision < 0 || prm->precision > 2) return fail(GW_EINVAL, "unknown precision");
+    if (prm->mode < 0 || prm->mode > 2) return fail(GW_EINVAL, "unknown mode");
+    if (prm->symmetric != 0 && prm->symmetric != 1) return fail(GW_EINVAL, "symmetric must be 0 or 1");
+    if (!(prm->tol_gamma >= 0.0)) return fail(GW_EINVAL, "tol_gamma must be >= 0");
+    return Status::ok();
+}
+
+static Status device_check(Ctx& c, const float* x, int64_t nx, const float* w, int64_t nw, const std::string& tag,
+                           double* wsum, const char* what) {
+    Status st;
+    const int blocks = 64;
+    int* flags = c.ws.get_t<int>(tag + "vflags", 4, &st);
+    double* part = c.ws.get_t<double>(tag + "vpart", blocks, &st);
+    if (!st.good()) return st;
+    GW_HIP(hipMemsetAsync(flags, 0, sizeof(int), c.stream));
+    GW_HIP(gwk::launch_validate(x, nx, w, nw, flags, part, blocks, c.stream));
+    int hf = 0;
+    std::vector<double> hp(blocks);
+    GW_HIP(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    GW_HIP(hipMemcpyAsync(hp.data(), part, blocks * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    GW_HIP(hipStreamSynchronize(c.stream));
+    if (hf & 1) return fail(GW_EINVAL, std::string("non-finite value in ") + what);
+    if (hf & 2) return fail(GW_EINVAL, std::string("weights of ") + what + " must be > 0");
+    double s = 0.0;
+    for (double v : hp) s += v;
+    if (std::fabs(s - 1.0) > 1e-5) return fail(GW_EINVAL, std::string("weights of ") + what + " must sum to 1");
+    *wsum = s;
+    return Status::ok();
+}
+
+Status validate_inputs(Ctx& c, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
+                       const float* b, const gw_params* prm, const std::string& tag) {
+    GW_TRY(check_params(prm));
+    if (!x || !a || !y || !b) return fail(GW_EINVAL, "NULL input pointer");
+    if (n < 1 || m < 1) return fail(GW_EINVAL, "n and m must be >= 1");
+    if (n > (int64_t)1 << 30 || m > (int64_t)1 << 30) return fail(GW_EINVAL, "n or m too large");
+    if (dx < 1 || dy < 1 || dx > MAX_DIM || dy > MAX_DIM) return fail(GW_EINVAL, "dimensions must be in [1, 256]");
+    (void)tag;
+    return Status::ok();
+}
+
+// ---------------------------------------------------------------------------
+// Lifting (Section 3 squared-norm example / Section 5 CNT embeddings)
+// ---------------------------------------------------------------------------
+
+Status lift_nystrom(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
+                    const std::string& tag);
+
+Status lift_side(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
+                 const std::string& tag) {
+    const SideCfg& s = c.side[side];
+    if (s.kind == GW_PEN_POWER) return lift_nystrom(c, side, x, n, d, w, X, n_pad, tag);
+    Status st;
+    double* part = c.ws.get_t<double>(tag + "cpart" + std::to_string(side), gwk::centre_part_doubles(n, d), &st);
+    double* mean = c.ws.get_t<double>(tag + "cmean" + std::to_string(side), d, &st);
+    if (!st.good()) return st;
+    GW_HIP(gwk::launch_centre(x, n, n_pad, d, d, w, part, mean, X, c.stream));
+    return Status::ok();
+}
+
+// ---------------------------------------------------------------------------
+// Solve
+// ---------------------------------------------------------------------------
+
+static constexpr double LOG2E = 1.4426950408889634;
+
+Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
+                    const float* b, const gw_params& prm, const float* gamma0, const float* f0, const float* g0,
+                    int pen_src, int pen_tgt, hipStream_t stream) {
+    st_ = stream;
+    prm_ = prm;
+    n_ = n;
+    m_ = m;
+    dx_ = dx;
+    dy_ = dy;
+    x_ = x;
+    y_ = y;
+    a_ = a;
+    b_ = b;
+    pen_[0] = pen_src;
+    pen_[1] = pen_tgt;
+    D_ = feature_dim(c_.side[0], dx);
+    E_ = feature_dim(c_.side[1], dy);
+    if (D_ < 1 || E_ < 1 || D_ > MAX_DIM || E_ > MAX_DIM) return fail(GW_EINVAL, "lifted dimension out of range");
+    prec_ = prm.precision;
+    if (D_ <= VALU_MAX_DIM) prec_ = PREC_F32;  // no contraction worth MFMA
+    if (prec_ == PREC_BF16X3 && D_ > MAX_DIM_BF16X3)
+        return fail(GW_EUNSUPPORTED, "split-BF16 supports D <= 128");
+    n_pad_ = (n + 31) / 32 * 32;
+    m_pad_ = (m + 31) / 32 * 32;
+    geo_ = gwk::pass_geometry(prec_, D_, n, m, 1);
+
+    // covariance geometry: one row group per macro tile, few column tiles
+    {
+        const int path = geo_.path;
+        const int rpg = gwk::cov_rows_per_group(path, prec_, D_, E_);
+        cov_rg_ = 1;
+        cov_mtr_ = (int)((n_pad_ + rpg - 1) / rpg);
+        const int nchc = (int)(m_pad_ / 32);
+        cov_tw_ = gwk::cov_tw(path, E_);
+        int want = std::max(1, (2048 + cov_mtr_ - 1) / cov_mtr_);
+        const size_t per_tile = (size_t)n_pad_ * (cov_tw_ + 2) * sizeof(float);
+        const int mem_cap = (int)std::max<size_t>(1, ((size_t)1 << 30) / per_tile);
+        want = std::min(want, std::min(mem_cap, nchc));
+        cov_bc_ = (nchc + want - 1) / want;
+        cov_mtc_ = (nchc + cov_bc_ - 1) / cov_bc_;
+    }
+    GW_TRY(buffers());
+
+    // weights: validation also gives their FP64 sums
+    double asum = 1.0, bsum = 1.0;
+    {
+        Status s1 = device_check(c_, x, n * (int64_t)dx, a, n, tag_ + "va", &asum, "source");
+        if (!s1.good()) return s1;
+        Status s2 = device_check(c_, y, m * (int64_t)dy, b, m, tag_ + "vb", &bsum, "target");
+        if (!s2.good()) return s2;
+    }
+    asum_ = asum;
+    bsum_ = bsum;
+
+    // lifting
+    GW_TRY(lift_side(c_, 0, x, n, dx, a, X_, n_pad_, tag_));
+    GW_TRY(lift_side(c_, 1, y, m, dy, b, Y_, m_pad_, tag_));
+    GW_HIP(gwk::launch_norms_logw(X_, n, n_pad_, D_, a, asum, xn_, la2_, st_));
+    GW_HIP(gwk::launch_norms_logw(Y_, m, m_pad_, E_, b, bsum, ym_, lb2_, st_));
+
+    // initial state
+    if (gamma0) {
+        GW_HIP(hipMemcpyAsync(gam_[0], gamma0, (size_t)D_ * E_ * sizeof(float), hipMemcpyDeviceToDevice, st_));
+    } else {
+        GW_HIP(hipMemsetAsync(gam_[0], 0, (size_t)D_ * E_ * sizeof(float), st_));
+    }
+    gcur_ = 0;
+    have_init_ = f0 && g0;
+    if (have_init_) {
+        GW_HIP(hipMemcpyAsync(f_, f0, n * sizeof(float), hipMemcpyDeviceToDevice, st_));
+        GW_HIP(hipMemcpyAsync(g_, g0, m * sizeof(float), hipMemcpyDeviceToDevice, st_));
+    }
+    GW_HIP(gwk::launch_ctl_init(ctl_, prm.mode, st_));
+
+    // row operand packs: features and |X|^2 slots once (potential slots are
+    // refreshed by the prologue and the combines)
+    if (geo_.path == 0) {
+        for (int p = 0; p < 2; ++p) {
+            GW_HIP(hipMemsetAsync(U_[p], 0, n_pad_ * sizeof(float), st_));
+            GW_HIP(hipMemsetAsync(Ul_[p], 0, n_pad_ * sizeof(float), st_));
+            GW_HIP(gwk::launch_pack(X_, n, n_pad_, D_, 1.0f, prec_, 0, U_[p], Ul_[p], xn_, packA_[p], st_));
+        }
+    }
+    eps_sched_.resize(prm.n_outer);
+    for (int t = 0; t < prm.n_outer; ++t) {
+        if (prm.n_outer == 1 || prm.eps_start == prm.eps_end)
+            eps_sched_[t] = prm.eps_start;
+        else
+            eps_sched_[t] = prm.eps_start * std::pow(prm.eps_end / prm.eps_start, (double)t / (prm.n_outer - 1));
+    }
+    t_ = 0;
+    done_ = false;
+    pa_ = pb_ = 0;
+    return Status::ok();
+}
+
+Status Solve::buffers() {
+    Status st;
+    auto& ws = c_.ws;
+    const std::string& T = tag_;
+    footprint_ = 0;
+    auto getf = [&](const char* nm, size_t cnt) -> float* {
+        footprint_ += cnt * 4;
+        return ws.get_t<float>(T + nm, cnt, &st);
+    };
+    auto getd = [&](const char* nm, size_t cnt) -> double* {
+        footprint_ += cnt * 8;
+        return ws.get_t<double>(T + nm, cnt, &st);
+    };
+    X_ = getf("X", (size_t)n_pad_ * D_);
+    Y_ = getf("Y", (size_t)m_pad_ * E_);
+    xn_ = getf("xn", n_pad_);
+    ym_ = getf("ym", m_pad_);
+    la2_ = getf("la2", n_pad_);
+    lb2_ = getf("lb2", m_pad_);
+    for (int p = 0; p < 2; ++p) {
+        U_[p] = getf(p ? "U1" : "U0", n_pad_);
+        V_[p] = getf(p ? "V1" : "V0", m_pad_);
+        Ul_[p] = getf(p ? "Ul1" : "Ul0", n_pad_);
+        Vl_[p] = getf(p ? "Vl1" : "Vl0", m_pad_);
+    }
+    if (geo_.path == 0) {
+        const size_t ba = pack_bytes(prec_, D_, n_pad_), bb = pack_bytes(prec_, D_, m_pad_);
+        packA_[0] = getf("pA0", ba / 4);
+        packA_[1] = getf("pA1", ba / 4);
+        packB_[0] = getf("pB0", bb / 4);
+        packB_[1] = getf("pB1", bb / 4);
+    }
+    Zs_ = getf("Zs", (size_t)m_pad_ * D_);
+    beta_ = getd("beta", m_pad_);
+    ms_ = getf("ms", m_pad_);
+    f_ = getf("f", n_pad_);
+    g_ = getf("g", m_pad_);
+    gam_[0] = getf("gam0", (size_t)D_ * E_);
+    gam_[1] = getf("gam1", (size_t)D_ * E_);
+    gam64_ = getd("gam64", (size_t)D_ * E_);
+    rp_ = getf("rp", (size_t)geo_.n_mt_c * n_pad_);
+    rp2_ = getf("rp2", (size_t)geo_.n_mt_c * n_pad_);
+    cp_ = getf("cp", (size_t)geo_.n_mt_r * m_pad_);
+    cp2_ = getf("cp2", (size_t)geo_.n_mt_r * m_pad_);
+    const int tw_max = std::max(gwk::cov_tw(geo_.path, E_), gwk::cov_tw(geo_.path, D_));
+    const int mtc_max = cov_mtc_;
+    const int64_t np_max = std::max(n_pad_, m_pad_);
+    Tp_ = getf("Tp", (size_t)mtc_max * np_max * tw_max);
+    crp_ = getf("crp", (size_t)mtc_max * np_max);
+    crmp_ = getf("crmp", (size_t)mtc_max * np_max);
+    rsum_ = getf("rsum", np_max);
+    rm_ = getf("rm", np_max);
+    part_ = getd("part", std::max(gwk::cov_reduce_part_doubles(n_, D_, E_), gwk::cov_reduce_part_doubles(m_, E_, D_)));
+    scal_ = getd("scal", 16);
+    ctl_ = (int*)getf("ctl", CTL_WORDS);
+    momx_ = getd("momx", 2 + D_ * D_ + D_);
+    momy_ = getd("momy", 2 + E_ * E_ + E_);
+    mompart_ = getd("mompart", std::max(gwk::moments_part_doubles(n_, D_), gwk::moments_part_doubles(m_, E_)));
+    return st;
+}
+
+Status Solve::inner_iteration(int k) {
+    (void)k;
+    gwk::Operands op{};
+    op.prec = prec_;
+    op.d = D_;
+    gwk::Partials pp{rp_, rp2_, cp_, cp2_};
+    auto set_ops = [&]() {
+        if (geo_.path == 0) {
+            op.A = packA_[pa_];
+            op.B = packB_[pb_];
+        } else {
+            op.X = X_;
+            op.xn = xn_;
+            op.U = U_[pa_];
+            op.Ul = Ul_[pa_];
+            op.Zs = Zs_;
+            op.ms = ym_;
+            op.V = V_[pb_];
+            op.Vl = Vl_[pb_];
+            op.kappa = (float)kappa_;
+        }
+    };
+    auto half = [&](int do_rows, int do_cols, float step) -> Status {
+        set_ops();
+        gwk::CombineArgs ca{};
+        ca.rp = rp_;
+        ca.rp2 = rp2_;
+        ca.cp = cp_;
+        ca.cp2 = cp2_;
+        ca.n_mt_c = geo_.n_mt_c;
+        ca.n_mt_r = geo_.n_mt_r;
+        ca.n = (int)n_;
+        ca.m = (int)m_;
+        ca.n_pad = (int)n_pad_;
+        ca.m_pad = (int)m_pad_;
+        ca.la2 = la2_;
+        ca.lb2 = lb2_;
+        ca.U_cur = U_[pa_];
+        ca.Ul_cur = Ul_[pa_];
+        ca.V_cur = V_[pb_];
+        ca.Vl_cur = Vl_[pb_];
+        ca.U_next = U_[1 - pa_];
+        ca.Ul_next = Ul_[1 - pa_];
+        ca.V_next = V_[1 - pb_];
+        ca.Vl_next = Vl_[1 - pb_];
+        ca.packA_next = geo_.path == 0 && do_rows ? packA_[1 - pa_] : nullptr;
+        ca.packB_next = geo_.path == 0 && do_cols ? packB_[1 - pb_] : nullptr;
+        ca.prec = prec_;
+        ca.d = D_;
+        ca.do_rows = do_rows;
+        ca.do_cols = do_cols;
+        ca.step = step;
+        ca.is_retry = 0;
+        GW_HIP(gwk::launch_pass(op, geo_, pp, ctl_, RUN_STAB, 0, st_));
+        GW_HIP(gwk::launch_pass(op, geo_, pp, ctl_, RUN_SAFE, 1, st_));
+        GW_HIP(gwk::launch_combine(ca, ctl_, RUN_ALWAYS, st_));
+        GW_HIP(gwk::launch_pass(op, geo_, pp, ctl_, RUN_RETRY, 1, st_));
+        ca.is_retry = 1;
+        GW_HIP(gwk::launch_combine(ca, ctl_, RUN_RETRY, st_));
+        return Status::ok();
+    };
+    if (prm_.symmetric) {
+        GW_TRY(half(1, 1, 0.5f));
+        pa_ ^= 1;
+        pb_ ^= 1;
+    } else {
+        GW_TRY(half(1, 0, 1.0f));
+        // the row half-step wrote U into the other parity; columns read it
+        pa_ ^= 1;
+        GW_TRY(half(0, 1, 1.0f));
+        pb_ ^= 1;
+    }
+    return Status::ok();
+}
+
+Status Solve::covariance(int rows_side, float* T_out, float* r_out, float* rm_out) {
+    gwk::CovOut out{Tp_, crp_, crmp_, 0};
+    if (rows_side == 0) {
+        out.tw = cov_tw_;
+        GW_HIP(gwk::launch_cov(geo_.path, prec_, D_, packA_[pa_], packB_[pb_], X_, xn_, U_[pa_], Ul_[pa_], Zs_,
+                               geo_.path == 1 ? ym_ : ms_, V_[pb_], Vl_[pb_], (float)kappa_, Y_, ym_, E_, n_pad_,
+                               m_pad_, cov_rg_, cov_bc_, cov_mtr_, cov_mtc_, out, st_));
+        GW_HIP(gwk::launch_cov_reduce(out, cov_mtc_, n_, n_pad_, X_, D_, xn_, E_, T_out, r_out, rm_out, part_, st_));
+        return Status::ok();
+    }
+    return fail(GW_EUNSUPPORTED, "column-side covariance is issued by the gradient path");
+}
+
+Status Solve::outer_step() {
+    if (done_) return Status::ok();
+    const int t = t_;
+    eps_t_ = eps_sched_[t];
+    kappa_ = LOG2E * 8.0 / eps_t_;
+    // prologue (Algorithm 1: Zbar_j = [Gamma_t Y_j, |Y_j|^2 / 2]); potentials
+    // rebased to the new temperature and Gamma in FP64
+    const int expanded = geo_.path == 0 ? 1 : 0;
+    const int first = t == 0 ? 1 : 0;
+    GW_HIP(gwk::launch_prologue_cols(Y_, m_, m_pad_, E_, D_, gam_[gcur_], ym_, lb2_, have_init_ ? g_ : nullptr, first,
+                                     expanded, kappa_, kappa_old_, Zs_, beta_, V_[pb_], Vl_[pb_], ms_, st_));
+    GW_HIP(gwk::launch_prologue_rows(n_, n_pad_, xn_, la2_, have_init_ ? f_ : nullptr, first, expanded, kappa_,
+                                     kappa_old_, U_[pa_], Ul_[pa_], st_));
+    if (geo_.path == 0) {
+        for (int p = 0; p < 2; ++p)
+            GW_HIP(gwk::launch_pack(Zs_, m_, m_pad_, D_, 1.0f, prec_, 1, V_[pb_], Vl_[pb_], ms_, packB_[p], st_));
+        GW_HIP(gwk::launch_pack_pot(U_[pa_], Ul_[pa_], n_pad_, D_, prec_, 0, packA_[pa_], st_));
+    }
+    kappa_old_ = kappa_;
+    // Sinkhorn at eps_t / 8 (Algorithm 3 or 2), warm-started
+    for (int k = 0; k < prm_.n_inner; ++k) GW_TRY(inner_iteration(k));
+    // covariance: Gamma_{t+1} = sum_ij pi_ij X_i Y_j^T
+    GW_TRY(covariance(0, nullptr, rsum_, rm_));
+    GW_HIP(gwk::launch_gamma_final(part_, n_, D_, E_, gam_[gcur_], gam64_, gam_[1 - gcur_], scal_, st_));
+    gcur_ ^= 1;
+    ++t_;
+    if (t_ >= prm_.n_outer) done_ = true;
+    if (!done_ && prm_.tol_gamma > 0.0) {
+        double d2 = 0.0;
+        GW_HIP(hipMemcpyAsync(&d2, scal_ + 3, sizeof(double), hipMemcpyDeviceToHost, st_));
+        GW_HIP(hipStreamSynchronize(st_));
+        if (std::sqrt(d2) <= prm_.tol_gamma) done_ = true;
+    }
+    return Status::ok();
+}
+
+Status Solve::finish(gw_result* out) {
+    Status st;
+    auto& ws = c_.ws;
+    // FP64 check of the final coupling (f_T, g_T, Gamma_{T-1})
+    double* r64 = ws.get_t<double>(tag_ + "r64", n_, &st);
+    double* kl64 = ws.get_t<double>(tag_ + "kl64", n_, &st);
+    double* c64 = ws.get_t<double>(tag_ + "c64", m_, &st);
+    if (!st.good()) return st;
+    if (geo_.path == 1) {
+        const float kap = (float)kappa_;
+        GW_HIP(gwk::launch_check64_direct(D_, X_, xn_, U_[pa_], Ul_[pa_], Zs_, ym_, V_[pb_], Vl_[pb_], kap, n_, m_,
+                                          la2_, lb2_, r64, kl64, st_));
+        GW_HIP(gwk::launch_check64_direct(D_, Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_, U_[pa_], Ul_[pa_], kap, m_, n_,
+                                          lb2_, nullptr, c64, nullptr, st_));
+    } else {
+        GW_HIP(gwk::launch_check64(prec_, D_, packA_[pa_], packB_[pb_], n_, n_pad_, m_, m_pad_, la2_, lb2_, r64, kl64,
+                                   st_));
+        GW_HIP(gwk::launch_check64(prec_, D_, packB_[pb_], packA_[pa_], m_, m_pad_, n_, n_pad_, lb2_, nullptr, c64,
+                                   nullptr, st_));
+    }
+    GW_HIP(gwk::launch_check_final(r64, kl64, n_, a_, c64, m_, b_, asum_, bsum_, scal_, st_));
+    // moments for C(alpha, beta)
+    GW_HIP(gwk::launch_moments(X_, n_, D_, a_, mompart_, momx_, st_));
+    GW_HIP(gwk::launch_moments(Y_, m_, E_, b_, mompart_, momy_, st_));
+    // outputs: potentials back in Algorithm 1's convention (cost units)
+    if (geo_.path == 1) {
+        if (out->f) GW_HIP(gwk::launch_epilogue(n_, U_[pa_], Ul_[pa_], la2_, nullptr, nullptr, 0, kappa_, out->f, st_));
+        if (out->g) GW_HIP(gwk::launch_epilogue(m_, V_[pb_], Vl_[pb_], lb2_, nullptr, nullptr, 0, kappa_, out->g, st_));
+    } else {
+        if (out->f) GW_HIP(gwk::launch_epilogue(n_, U_[pa_], Ul_[pa_], la2_, xn_, nullptr, 1, kappa_, out->f, st_));
+        if (out->g) GW_HIP(gwk::launch_epilogue(m_, V_[pb_], Vl_[pb_], lb2_, nullptr, beta_, 2, kappa_, out->g, st_));
+    }
+    if (out->gamma)
+        GW_HIP(hipMemcpyAsync(out->gamma, gam_[gcur_], (size_t)D_ * E_ * sizeof(float), hipMemcpyDeviceToDevice,
+                              st_));
+    std::vector<double> hs(16), mx(2 + D_ * D_ + D_), my(2 + E_ * E_ + E_);
+    int hctl[CTL_WORDS];
+    GW_HIP(hipMemcpyAsync(hs.data(), scal_, 16 * sizeof(double), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipMemcpyAsync(mx.data(), momx_, mx.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipMemcpyAsync(my.data(), momy_, my.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipMemcpyAsync(hctl, ctl_, sizeof(hctl), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipStreamSynchronize(st_));
+    auto cpart = [](const std::vector<double>& mo, int d) {
+        double s = mo[0], m4 = mo[1], sig2 = 0.0;
+        for (int k = 0; k < d * d; ++k) sig2 += mo[2 + k] * mo[2 + k];
+        return 2.0 * m4 + 4.0 * sig2 + 2.0 * s * s;
+    };
+    // Lemma C.1: C = iint|x-x'|^4 + iint|y-y'|^4 - 4 s_x s_y; for centred
+    // measures iint |x - x'|^4 = 2 m4 + 4 |Sigma|^2 + 2 s^2.
+    const double C = cpart(mx, D_) + cpart(my, E_) - 4.0 * mx[0] * my[0];
+    out->constant_c = C;
+    out->sum_pi_nm = hs[1];
+    out->loss_lift = C - 8.0 * hs[2] - 4.0 * hs[1];
+    out->kl = hs[5];
+    out->marginal_err = hs[4];
+    out->egw_objective = out->loss_lift + eps_t_ * hs[5];
+    out->gamma_step = std::sqrt(hs[3]);
+    out->eps_final = eps_t_;
+    out->outer_done = t_;
+    out->dim_x = D_;
+    out->dim_y = E_;
+    out->safe_iters = hctl[CTL_SAFE_ITERS];
+    if (hctl[CTL_NUMERIC] || !std::isfinite(out->loss_lift) || !std::isfinite(out->kl))
+        return fail(GW_ENUMERIC, "non-finite values in the Sinkhorn iteration");
+    return Status::ok();
+}
+
+}  // namespace gwr

@@ -1,0 +1,192 @@
+// Host runtime of the CNT-GW library: context, workspace and the solver
+// state machine (one Algorithm 1 solve).  Shared by the C ABI and the
+// serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gw.h"
+#include "gw_kernels.h"
+#include "gw_layout.h"
+#include "gw_prep.h"
+
+namespace gwr {
+
+struct Status {
+    gw_status code = GW_OK;
+    std::string msg;
+    static Status ok() { return Status(); }
+    bool good() const { return code == GW_OK; }
+};
+Status fail(gw_status c, const std::string& m);
+Status hip_fail(hipError_t e, const char* where);
+
+#define GW_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e__ = (call);                          \
+        if (e__ != hipSuccess) return hip_fail(e__, #call); \
+    } while (0)
+#define GW_TRY(expr)                     \
+    do {                                 \
+        Status s__ = (expr);             \
+        if (!s__.good()) return s__;     \
+    } while (0)
+
+// Grow-only device buffers addressed by name, with a byte limit.
+class Workspace {
+   public:
+    explicit Workspace(size_t limit = 0) : limit_(limit) {}
+    ~Workspace();
+    // Returns nullptr (and sets status) when the limit would be exceeded or
+    // the allocation fails.
+    void* get(const std::string& name, size_t bytes, Status* st);
+    template <class T>
+    T* get_t(const std::string& name, size_t count, Status* st) {
+        return (T*)get(name, count * sizeof(T), st);
+    }
+    void release_all();
+    void release_prefix(const std::string& prefix);
+    size_t total() const { return total_; }
+    size_t limit() const { return limit_; }
+    void set_limit(size_t l) { limit_ = l; }
+
+   private:
+    struct Buf {
+        void* p = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> bufs_;
+    size_t total_ = 0;
+    size_t limit_ = 0;
+};
+
+// Frozen landmark kernel PCA of one side (GW_PEN_POWER).
+struct Landmarks {
+    bool fitted = false;
+    int n_l = 0;       // landmarks
+    int d_in = 0;      // input dimension
+    int dim = 0;       // lifted dimension D
+    float* pts = nullptr;   // n_l x d_in (device)
+    float* W = nullptr;     // n_l x D: -V_ld / (2 sqrt(lambda_d)), 0 for dropped
+    float* chat = nullptr;  // n_l: landmark column means of the cost
+    float* sumW = nullptr;  // D: sum_l W_ld
+    double cbarbar = 0.0;   // grand mean of the landmark cost
+    std::vector<double> lambda;  // eigenvalues kept (host copy, diagnostics)
+};
+
+struct SideCfg {
+    int kind = GW_PEN_SQEUCLID;
+    double p = 1.0;
+    int lifted_dim = 0;
+    int n_landmarks = 0;
+    uint64_t seed = 0;
+    std::vector<int64_t> explicit_idx;
+    Landmarks lm;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    std::string err;
+    SideCfg side[2];
+    void* rocblas = nullptr;  // rocblas_handle, created on first eigensolve
+    std::mutex mu;
+};
+
+int feature_dim(const SideCfg& s, int d);
+
+// Lift points of one side into centred features X (n_pad x D, padded rows
+// zero).  Fits landmarks on first use for GW_PEN_POWER.
+Status lift_side(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
+                 const std::string& tag);
+
+// Host-side validation of a problem; launches the device checks and waits.
+Status validate_inputs(Ctx& c, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
+                       const float* b, const gw_params* prm, const std::string& tag);
+
+// One Algorithm 1 solve as a resumable state machine.
+class Solve {
+   public:
+    Solve(Ctx& c, const std::string& tag) : c_(c), tag_(tag) {}
+    Status setup(const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
+                 const float* b, const gw_params& prm, const float* gamma0, const float* f0, const float* g0,
+                 int pen_src, int pen_tgt, hipStream_t stream);
+    // Enqueue outer step t (prologue, n_inner Sinkhorn iterations,
+    // covariance).  Returns false when the solve has finished.
+    Status outer_step();
+    bool done() const { return done_; }
+    int outer_done() const { return t_; }
+    // FP64 final check and result readback (blocks on the stream).
+    Status finish(gw_result* out);
+    // Gradients of the final state (after finish).
+    Status gradients(float* grad_x, float* grad_a, float* grad_y, float* grad_b);
+    size_t footprint() const { return footprint_; }
+    int64_t n() const { return n_; }
+    int64_t m() const { return m_; }
+    double entries_per_outer() const { return (double)n_ * (double)m_ * prm_.n_inner; }
+
+   private:
+    Status buffers();
+    Status inner_iteration(int k);
+    Status covariance(int rows_side, float* T_out, float* r_out, float* rm_out);
+
+    Ctx& c_;
+    std::string tag_;
+    hipStream_t st_ = nullptr;
+    gw_params prm_{};
+    int64_t n_ = 0, m_ = 0, n_pad_ = 0, m_pad_ = 0;
+    int dx_ = 0, dy_ = 0, D_ = 0, E_ = 0;
+    int prec_ = 0;
+    int pen_[2] = {0, 0};
+    const float* x_ = nullptr;
+    const float* y_ = nullptr;
+    const float* a_ = nullptr;
+    const float* b_ = nullptr;
+    gwk::Geometry geo_{};
+    int cov_rg_ = 1, cov_bc_ = 1, cov_mtr_ = 1, cov_mtc_ = 1;
+    int t_ = 0;
+    bool done_ = false;
+    int pa_ = 0, pb_ = 0;      // pack / potential parities
+    double eps_t_ = 0.0, kappa_ = 0.0;
+    double asum_ = 1.0, bsum_ = 1.0;
+    size_t footprint_ = 0;
+    std::vector<double> eps_sched_;
+    // device buffers
+    float *X_ = nullptr, *Y_ = nullptr, *xn_ = nullptr, *ym_ = nullptr, *la2_ = nullptr, *lb2_ = nullptr;
+    void* packA_[2] = {nullptr, nullptr};
+    void* packB_[2] = {nullptr, nullptr};
+    // potentials in log2 units as FP32 (hi, lo) pairs, two parities
+    float *U_[2] = {nullptr, nullptr}, *V_[2] = {nullptr, nullptr};
+    float *Ul_[2] = {nullptr, nullptr}, *Vl_[2] = {nullptr, nullptr};
+    float *Zs_ = nullptr, *ms_ = nullptr;
+    double* beta_ = nullptr;
+    float *f_ = nullptr, *g_ = nullptr;  // warm-start input / output staging
+    bool have_init_ = false;
+    double kappa_old_ = 0.0;
+    float *gam_[2] = {nullptr, nullptr};
+    int gcur_ = 0;
+    double* gam64_ = nullptr;
+    float *rp_ = nullptr, *rp2_ = nullptr, *cp_ = nullptr, *cp2_ = nullptr;
+    float *Tp_ = nullptr, *crp_ = nullptr, *crmp_ = nullptr;
+    float *T_ = nullptr, *rsum_ = nullptr, *rm_ = nullptr;
+    double* part_ = nullptr;
+    double* scal_ = nullptr;
+    int* ctl_ = nullptr;
+    double *momx_ = nullptr, *momy_ = nullptr, *mompart_ = nullptr;
+    int cov_tw_ = 0;
+};
+
+}  // namespace gwr
+
+namespace gwr {
+void release_landmarks(Ctx& c);
+Status lift_nystrom(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
+                    const std::string& tag);
+}  // namespace gwr

@@ -1,0 +1,116 @@
+"""GPU parity of full solves against the FP64 oracle (called through the C
+ABI).  Tolerances: relative loss error <= 1e-5 for FP32 and split-BF16,
+<= 1e-3 for BF16 (plain BF16 feature products)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gw_oracle as O
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(v):
+    return torch.tensor(np.asarray(v, dtype=np.float32), device="cuda")
+
+
+def f32(v):
+    return np.asarray(v, dtype=np.float32).astype(np.float64)
+
+
+def test_config1_plain_fp32(gw):
+    prob = synth.config1_plain()
+    with open(os.path.join(GOLD, "config1_oracle.json")) as fh:
+        gold = json.load(fh)
+    ctx = gw.Context()
+    ctx.set_penalty(2, "sqeuclid")
+    res = ctx.solve(dev(prob.x), dev(prob.a), dev(prob.y), dev(prob.b), 0.01, 0.01, 20, 50)
+    rel = abs(res["loss_lift"] - gold["loss_lift"]) / abs(gold["loss_lift"])
+    gam = res["gamma"].cpu().numpy()
+    print("C1 loss", res["loss_lift"], gold["loss_lift"], "rel", rel, "err", res["marginal_err"],
+          gold["marginal_error"], "safe_iters", res["safe_iters"], "gamma", gam.ravel(), np.ravel(gold["gamma"]))
+    assert rel < 1e-5
+    assert np.abs(gam - np.array(gold["gamma"])).max() < 1e-5 * np.abs(gold["gamma"]).max() * 10
+    assert abs(res["marginal_err"] - gold["marginal_error"]) < 1e-6
+
+
+def _feature_problem(seed, n, m, d, e, scale=1.0):
+    """Features of norm ~ scale; the target is a noisy orthogonal image of a
+    subsample of the source, so the GW problem has a clear matching."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d)) * (scale / np.sqrt(d))
+    q, _ = np.linalg.qr(rng.standard_normal((max(d, e), max(d, e))))
+    idx = rng.choice(n, size=m, replace=m > n)
+    Y = (X[idx] @ q[:d, :e]) + 0.05 * scale / np.sqrt(e) * rng.standard_normal((m, e))
+    a = rng.dirichlet(np.ones(n) * 5)
+    b = rng.dirichlet(np.ones(m) * 5)
+    a32, b32 = f32(a), f32(b)
+    a32 /= a32.sum()
+    b32 /= b32.sum()
+    return O.centre(f32(X), a32), a32, O.centre(f32(Y), b32), b32
+
+
+def _run_pair(gw, X, a, Y, b, eps, n_outer, n_inner, **kw):
+    ctx = gw.Context()
+    ctx.set_penalty(2, "features")
+    return ctx.solve(dev(X), dev(a), dev(Y), dev(b), eps, eps, n_outer, n_inner, **kw)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-5), ("bf16", 1e-3)])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_features_mfma_path(gw, prec, tol, symmetric):
+    X, a, Y, b = _feature_problem(7, 333, 290, 32, 32)
+    eps = 0.1
+    ref = O.cnt_gw(a, b, X, Y, eps, eps, 4, 50, symmetric=symmetric)
+    ref_loss = O.lifted_loss(X, Y, a, b, ref.pi)
+    res = _run_pair(gw, X, a, Y, b, eps, 4, 50, precision=prec, symmetric=symmetric)
+    rel = abs(res["loss_lift"] - ref_loss) / abs(ref_loss)
+    gdiff = float(np.abs(res["gamma"].cpu().numpy() - ref.gamma).max() / np.abs(ref.gamma).max())
+    ferr = float(np.abs(res["f"].cpu().numpy() - ref.f).max())
+    gerr = float(res["marginal_err"])
+    oerr = float(O.marginal_error(ref.pi, a, b))
+    print(prec, "sym" if symmetric else "alt", "loss", res["loss_lift"], ref_loss, "rel", rel, "gamma rel", gdiff,
+          "f err", ferr, "err", gerr, oerr, "kl", res["kl"], O.kl_divergence(ref.pi, a, b), "safe", res["safe_iters"])
+    assert rel < tol
+    # marginal violation where the oracle itself is converged: <= 1e-6 for
+    # FP32; the BF16-MFMA accumulation of the expanded exponent leaves a
+    # measured floor of ~3e-6 at this size for both BF16 forms
+    if oerr <= 1e-7:
+        assert gerr <= (1e-6 if prec == "fp32" else 5e-6)
+
+
+@pytest.mark.parametrize("mode", ["safe", "stabilised", "auto"])
+def test_modes_agree(gw, mode):
+    X, a, Y, b = _feature_problem(8, 200, 257, 48, 40)
+    eps = 0.2
+    ref = O.cnt_gw(a, b, X, Y, eps, eps, 3, 40)
+    ref_loss = O.lifted_loss(X, Y, a, b, ref.pi)
+    res = _run_pair(gw, X, a, Y, b, eps, 3, 40, precision="fp32", mode=mode)
+    rel = abs(res["loss_lift"] - ref_loss) / abs(ref_loss)
+    print(mode, "rel", rel, "safe iters", res["safe_iters"])
+    assert rel < 1e-5
+    if mode == "safe":
+        assert res["safe_iters"] == 3 * 40
+    if mode == "stabilised":
+        assert res["safe_iters"] == 0
+
+
+def test_valu_path_small_dims(gw):
+    """D < 16 runs the VALU direct-form kernels; mixed dimensions 3 -> 5.
+    Gamma_0 is a landmark initialisation (the paper's user-chosen basin,
+    Section 6) so that both sides follow the same basin of this symmetric
+    problem."""
+    X, a, Y, b = _feature_problem(9, 150, 170, 3, 5)
+    eps = 0.05
+    g0 = X[:20].T @ Y[:20] / 20.0
+    ref = O.cnt_gw(a, b, X, Y, eps, eps, 5, 60, gamma0=g0)
+    ref_loss = O.lifted_loss(X, Y, a, b, ref.pi)
+    res = _run_pair(gw, X, a, Y, b, eps, 5, 60, gamma0=dev(g0))
+    rel = abs(res["loss_lift"] - ref_loss) / abs(ref_loss)
+    print("valu rel", rel, "gamma", np.abs(res["gamma"].cpu().numpy() - ref.gamma).max())
+    assert rel < 1e-5
