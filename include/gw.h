@@ -180,6 +180,36 @@ void gw_destroy(gw_ctx* ctx);
 const char* gw_last_error(const gw_ctx* ctx);
 
 /* ---------------------------------------------------------------------- */
+/* Profiling: HIP events around each kernel class on the context stream.   */
+/* ---------------------------------------------------------------------- */
+
+typedef enum {
+    GW_PROF_PASS_STAB = 0,   /* stabilised Sinkhorn pass launches */
+    GW_PROF_PASS_SAFE = 1,   /* safe / retry pass launches (may be no-ops) */
+    GW_PROF_COMBINE = 2,     /* partial combines + potential updates */
+    GW_PROF_COVARIANCE = 3,  /* covariance pass and Gamma reduction */
+    GW_PROF_PROLOGUE = 4,    /* per-outer-step prologue and packing */
+    GW_PROF_CHECK = 5,       /* FP64 final check */
+    GW_PROF_LIFT = 6,        /* feature lifting */
+    GW_PROF_GRAD = 7,        /* backward pass */
+    GW_PROF_CLASSES = 8
+} gw_prof_class;
+
+typedef struct {
+    int64_t launches[GW_PROF_CLASSES];
+    double milliseconds[GW_PROF_CLASSES];   /* summed event intervals */
+    int64_t entries_per_pass;               /* N * M of the last solve */
+} gw_profile;
+
+/* Enable (1) or disable (0) event timing; either call resets the counters.
+   Timing adds an event pair per recorded launch. */
+gw_status gw_set_profiling(gw_ctx* ctx, int enable);
+
+/* Synchronise the context stream and return the counters accumulated since
+   the last gw_set_profiling. */
+gw_status gw_get_profile(gw_ctx* ctx, gw_profile* out);
+
+/* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of independent solves on one GPU.         */
 /* ---------------------------------------------------------------------- */
 

@@ -165,13 +165,6 @@ def landmark_features(x: np.ndarray, a: np.ndarray, lm: Landmarks) -> np.ndarray
     return centre(kernel_proj(x, lm), a)
 
 
-def choose_landmarks(n: int, n_landmarks: int, seed: int) -> np.ndarray:
-    """Indices of the landmark subset: the first n_l entries of a seeded
-    permutation (the same rule the library documents)."""
-    perm = np.random.default_rng(seed).permutation(n)
-    return np.sort(perm[: min(n_landmarks, n)])
-
-
 # --------------------------------------------------------------------------
 # Entropic OT
 # --------------------------------------------------------------------------

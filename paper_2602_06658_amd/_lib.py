@@ -79,6 +79,18 @@ class GwServerStats(ctypes.Structure):
     ]
 
 
+GW_PROF_CLASSES = 8
+PROF_NAMES = ["pass_stab", "pass_safe", "combine", "covariance", "prologue", "check", "lift", "grad"]
+
+
+class GwProfile(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_int64 * GW_PROF_CLASSES),
+        ("milliseconds", ctypes.c_double * GW_PROF_CLASSES),
+        ("entries_per_pass", ctypes.c_int64),
+    ]
+
+
 # name -> (restype, argtypes); mirrors include/gw.h
 SIGNATURES = {
     "gw_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]),
@@ -97,6 +109,8 @@ SIGNATURES = {
                                         ctypes.POINTER(GwResult), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gw_destroy": (None, [ctypes.c_void_p]),
+    "gw_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "gw_get_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GwProfile)]),
     "gw_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "gw_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t,
                                         ctypes.POINTER(ctypes.c_void_p)]),

@@ -82,6 +82,17 @@ class Context:
         if rc != L.GW_OK:
             raise L.GWError(rc, self.lib.gw_last_error(self.h).decode())
 
+    def set_profiling(self, enable: bool = True):
+        self._check(self.lib.gw_set_profiling(self.h, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        pr = L.GwProfile()
+        self._check(self.lib.gw_get_profile(self.h, ctypes.byref(pr)))
+        out = {name: {"launches": int(pr.launches[k]), "ms": float(pr.milliseconds[k])}
+               for k, name in enumerate(L.PROF_NAMES)}
+        out["entries_per_pass"] = int(pr.entries_per_pass)
+        return out
+
     def set_penalty(self, side: int, kind="sqeuclid", p: float = 1.0, lifted_dim: int = 0,
                     n_landmarks: int = 0, seed: int = 0):
         k = _PEN[kind] if isinstance(kind, str) else int(kind)

@@ -141,6 +141,30 @@ gw_status gw_loss_and_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const
     return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, grad_x, grad_a, grad_y, grad_b, true);
 }
 
+gw_status gw_set_profiling(gw_ctx* ctx, int enable) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    ctx->c.prof.reset();
+    ctx->c.prof.on = enable != 0;
+    return ret(ctx, Status::ok());
+}
+
+gw_status gw_get_profile(gw_ctx* ctx, gw_profile* out) {
+    if (!ctx || !out) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    (void)hipSetDevice(ctx->c.device);
+    Status st = ctx->c.prof.collect(ctx->c.stream);
+    if (!st.good()) return ret(ctx, st);
+    for (int k = 0; k < GW_PROF_CLASSES; ++k) {
+        out->launches[k] = ctx->c.prof.launches[k];
+        out->milliseconds[k] = ctx->c.prof.ms[k];
+    }
+    out->entries_per_pass = ctx->c.prof.entries;
+    return ret(ctx, Status::ok());
+}
+
 void gw_destroy(gw_ctx* ctx) {
     if (!ctx) return;
     {

@@ -33,6 +33,7 @@ hipError_t launch_prologue_rows(int64_t n, int64_t n_pad, const float* xnorm, co
 // columns (beta).
 hipError_t launch_epilogue(int64_t n, const float* Uh, const float* Ul, const float* lw2, const float* xnorm,
                            const double* beta, int kind, double kappa, float* f, hipStream_t stream);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream);
 size_t moments_part_doubles(int64_t n, int d);
 hipError_t launch_moments(const float* X, int64_t n, int d, const float* w, double* part, double* out,
                           hipStream_t stream);

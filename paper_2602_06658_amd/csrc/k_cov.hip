@@ -494,52 +494,88 @@ __device__ __forceinline__ float pack_elem(const void* pack, int prec, int units
     return bf16_bits_to_f32(((const uint16_t*)pack)[bf16_pack_off(row, k, units)]);
 }
 
+// 64 x 64 tiles of (row, column) entries; K consumed in blocks of 32
+// decoded to float in LDS; each thread owns a 4 x 4 block of entries.
+constexpr int CK_T = 64, CK_KB = 32;
+
 __global__ void __launch_bounds__(256) k_check64(int prec, int units, int K, const void* A, const void* B, int64_t n,
                                                  int64_t m, const float* la2, const float* lb2, double* rsum,
                                                  double* kl) {
-    extern __shared__ float bsh[];  // 32 x (K + 1)
-    __shared__ float lbs[32];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool act = i < n;
-    double rs = 0.0, klr = 0.0;
-    const double lai = act ? (double)la2[i] : 0.0;
-    const int64_t nchunks = (m + 31) / 32;
-    for (int64_t c = 0; c < nchunks; ++c) {
-        __syncthreads();
-        for (int u = threadIdx.x; u < 32 * K; u += blockDim.x) {
-            const int j = u / K, k = u - j * K;
-            bsh[j * (K + 1) + k] = pack_elem(B, prec, units, (int)(c * 32 + j), k);
-        }
-        if (threadIdx.x < 32) lbs[threadIdx.x] = lb2 ? lb2[c * 32 + threadIdx.x] : 0.f;
-        __syncthreads();
-        if (!act) continue;
-        double acc[32];
+    __shared__ float As[CK_T][CK_KB + 1];
+    __shared__ float Bs[CK_T][CK_KB + 1];
+    __shared__ float lbs[CK_T];
+    __shared__ double red[2][16][CK_T];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * CK_T;
+    double rs[4] = {0, 0, 0, 0}, kr[4] = {0, 0, 0, 0};
+    double la[4];
 #pragma unroll
-        for (int j = 0; j < 32; ++j) acc[j] = 0.0;
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            float av[16];
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = r0 + ty * 4 + u;
+        la[u] = (i < n && kl) ? (double)la2[i] : 0.0;
+    }
+    for (int64_t c0 = 0; c0 < m; c0 += CK_T) {
+        double acc[4][4];
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) av[kk] = k0 + kk < K ? pack_elem(A, prec, units, (int)i, k0 + kk) : 0.f;
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                const float* br = bsh + j * (K + 1) + k0;
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int k0 = 0; k0 < K; k0 += CK_KB) {
+            __syncthreads();
+            for (int e = tid; e < CK_T * CK_KB; e += 256) {
+                const int rr = e / CK_KB, kk = e - rr * CK_KB;
+                const int64_t i = r0 + rr, j = c0 + rr;
+                const int k = k0 + kk;
+                As[rr][kk] = (i < n && k < K) ? pack_elem(A, prec, units, (int)i, k) : 0.f;
+                Bs[rr][kk] = (j < m && k < K) ? pack_elem(B, prec, units, (int)j, k) : 0.f;
+            }
+            if (tid < CK_T) lbs[tid] = (lb2 && c0 + tid < m) ? lb2[c0 + tid] : 0.f;
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < CK_KB; ++kk) {
+                double av[4], bv[4];
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk)
-                    if (k0 + kk < K) acc[j] = fma((double)av[kk], (double)br[kk], acc[j]);
+                for (int u = 0; u < 4; ++u) {
+                    av[u] = (double)As[ty * 4 + u][kk];
+                    bv[u] = (double)Bs[tx * 4 + u][kk];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
             }
         }
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            if (c * 32 + j < m) {
-                const double p = exp2(acc[j]);
-                rs += p;
-                if (kl && p > 0.0) klr += p * (acc[j] - lai - (double)lbs[j]);
+        for (int v = 0; v < 4; ++v) {
+            const int64_t j = c0 + tx * 4 + v;
+            if (j >= m) continue;
+            const double lbj = (double)lbs[tx * 4 + v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double p = exp2(acc[u][v]);
+                rs[u] += p;
+                if (kl && p > 0.0) kr[u] += p * (acc[u][v] - la[u] - lbj);
             }
         }
     }
-    if (act) {
-        rsum[i] = rs;
-        if (kl) kl[i] = klr * 0.6931471805599453;
+    // reduce over the 16 threads sharing rows, fixed order
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        red[0][tx][ty * 4 + u] = rs[u];
+        red[1][tx][ty * 4 + u] = kr[u];
+    }
+    __syncthreads();
+    if (tid < CK_T) {
+        const int64_t i = r0 + tid;
+        double s = 0.0, q = 0.0;
+        for (int t = 0; t < 16; ++t) {
+            s += red[0][t][tid];
+            q += red[1][t][tid];
+        }
+        if (i < n) {
+            rsum[i] = s;
+            if (kl) kl[i] = q * 0.6931471805599453;
+        }
     }
 }
 
@@ -550,9 +586,8 @@ hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols,
     (void)m_pad;
     const int K = pack_k(prec, d);
     const int units = pack_units(prec, d);
-    const size_t lds = (size_t)32 * (K + 1) * sizeof(float);
-    hipLaunchKernelGGL(k_check64, dim3((unsigned)((n + 255) / 256)), dim3(256), lds, stream, prec, units, K, Arows,
-                       Bcols, n, m, la2, lb2, rsum, kl);
+    hipLaunchKernelGGL(k_check64, dim3((unsigned)((n + CK_T - 1) / CK_T)), dim3(256), 0, stream, prec, units, K,
+                       Arows, Bcols, n, m, la2, lb2, rsum, kl);
     return hipGetLastError();
 }
 

@@ -337,6 +337,17 @@ hipError_t launch_epilogue(int64_t n, const float* Uh, const float* Ul, const fl
     return hipGetLastError();
 }
 
+// Fill a float array (used to give padded potentials -inf in both parities).
+__global__ void k_fill(float* p, int64_t n, float v) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // FP64 moments of centred features with weights w:
 //   s = sum w |X|^2, m4 = sum w |X|^4, Sigma = sum w X X^T (d x d),

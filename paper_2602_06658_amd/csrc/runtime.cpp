@@ -77,6 +77,75 @@ void Workspace::release_prefix(const std::string& prefix) {
 }
 
 // ---------------------------------------------------------------------------
+// Profiler
+// ---------------------------------------------------------------------------
+
+hipEvent_t Profiler::take() {
+    if (!pool_.empty()) {
+        hipEvent_t e = pool_.back();
+        pool_.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void Profiler::begin(int cls, hipStream_t s) {
+    if (!on) return;
+    cur_.a = take();
+    cur_.b = take();
+    cur_.cls = cls;
+    (void)hipEventRecord(cur_.a, s);
+}
+
+void Profiler::end(hipStream_t s) {
+    if (!on) return;
+    (void)hipEventRecord(cur_.b, s);
+    pairs_.push_back(cur_);
+}
+
+Status Profiler::collect(hipStream_t s) {
+    GW_HIP(hipStreamSynchronize(s));
+    for (auto& p : pairs_) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+            ms[p.cls] += t;
+            launches[p.cls] += 1;
+        }
+        pool_.push_back(p.a);
+        pool_.push_back(p.b);
+    }
+    pairs_.clear();
+    return Status::ok();
+}
+
+void Profiler::reset() {
+    for (auto& p : pairs_) {
+        pool_.push_back(p.a);
+        pool_.push_back(p.b);
+    }
+    pairs_.clear();
+    for (int k = 0; k < GW_PROF_CLASSES; ++k) {
+        launches[k] = 0;
+        ms[k] = 0.0;
+    }
+}
+
+Profiler::~Profiler() {
+    reset();
+    for (auto e : pool_) (void)hipEventDestroy(e);
+}
+
+#define GW_PROF(cls, call)               \
+    do {                                 \
+        c_.prof.begin((cls), st_);       \
+        hipError_t pe__ = (call);        \
+        c_.prof.end(st_);                \
+        if (pe__ != hipSuccess) return hip_fail(pe__, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
 // Validation
 // ---------------------------------------------------------------------------
 
@@ -212,8 +281,10 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
     bsum_ = bsum;
 
     // lifting
+    c_.prof.begin(GW_PROF_LIFT, st_);
     GW_TRY(lift_side(c_, 0, x, n, dx, a, X_, n_pad_, tag_));
     GW_TRY(lift_side(c_, 1, y, m, dy, b, Y_, m_pad_, tag_));
+    c_.prof.end(st_);
     GW_HIP(gwk::launch_norms_logw(X_, n, n_pad_, D_, a, asum, xn_, la2_, st_));
     GW_HIP(gwk::launch_norms_logw(Y_, m, m_pad_, E_, b, bsum, ym_, lb2_, st_));
 
@@ -230,15 +301,20 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
         GW_HIP(hipMemcpyAsync(g_, g0, m * sizeof(float), hipMemcpyDeviceToDevice, st_));
     }
     GW_HIP(gwk::launch_ctl_init(ctl_, prm.mode, st_));
+    // padded rows and columns keep -inf potentials in both parities (the
+    // combines only ever write real rows and columns)
+    for (int p = 0; p < 2; ++p) {
+        GW_HIP(gwk::launch_fill(U_[p], n_pad_, -INFINITY, st_));
+        GW_HIP(gwk::launch_fill(V_[p], m_pad_, -INFINITY, st_));
+        GW_HIP(gwk::launch_fill(Ul_[p], n_pad_, 0.f, st_));
+        GW_HIP(gwk::launch_fill(Vl_[p], m_pad_, 0.f, st_));
+    }
 
     // row operand packs: features and |X|^2 slots once (potential slots are
     // refreshed by the prologue and the combines)
     if (geo_.path == 0) {
-        for (int p = 0; p < 2; ++p) {
-            GW_HIP(hipMemsetAsync(U_[p], 0, n_pad_ * sizeof(float), st_));
-            GW_HIP(hipMemsetAsync(Ul_[p], 0, n_pad_ * sizeof(float), st_));
+        for (int p = 0; p < 2; ++p)
             GW_HIP(gwk::launch_pack(X_, n, n_pad_, D_, 1.0f, prec_, 0, U_[p], Ul_[p], xn_, packA_[p], st_));
-        }
     }
     eps_sched_.resize(prm.n_outer);
     for (int t = 0; t < prm.n_outer; ++t) {
@@ -367,12 +443,12 @@ Status Solve::inner_iteration(int k) {
         ca.do_cols = do_cols;
         ca.step = step;
         ca.is_retry = 0;
-        GW_HIP(gwk::launch_pass(op, geo_, pp, ctl_, RUN_STAB, 0, st_));
-        GW_HIP(gwk::launch_pass(op, geo_, pp, ctl_, RUN_SAFE, 1, st_));
-        GW_HIP(gwk::launch_combine(ca, ctl_, RUN_ALWAYS, st_));
-        GW_HIP(gwk::launch_pass(op, geo_, pp, ctl_, RUN_RETRY, 1, st_));
+        GW_PROF(GW_PROF_PASS_STAB, gwk::launch_pass(op, geo_, pp, ctl_, RUN_STAB, 0, st_));
+        GW_PROF(GW_PROF_PASS_SAFE, gwk::launch_pass(op, geo_, pp, ctl_, RUN_SAFE, 1, st_));
+        GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_ALWAYS, st_));
+        GW_PROF(GW_PROF_PASS_SAFE, gwk::launch_pass(op, geo_, pp, ctl_, RUN_RETRY, 1, st_));
         ca.is_retry = 1;
-        GW_HIP(gwk::launch_combine(ca, ctl_, RUN_RETRY, st_));
+        GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_RETRY, st_));
         return Status::ok();
     };
     if (prm_.symmetric) {
@@ -411,6 +487,7 @@ Status Solve::outer_step() {
     // rebased to the new temperature and Gamma in FP64
     const int expanded = geo_.path == 0 ? 1 : 0;
     const int first = t == 0 ? 1 : 0;
+    c_.prof.begin(GW_PROF_PROLOGUE, st_);
     GW_HIP(gwk::launch_prologue_cols(Y_, m_, m_pad_, E_, D_, gam_[gcur_], ym_, lb2_, have_init_ ? g_ : nullptr, first,
                                      expanded, kappa_, kappa_old_, Zs_, beta_, V_[pb_], Vl_[pb_], ms_, st_));
     GW_HIP(gwk::launch_prologue_rows(n_, n_pad_, xn_, la2_, have_init_ ? f_ : nullptr, first, expanded, kappa_,
@@ -421,11 +498,14 @@ Status Solve::outer_step() {
         GW_HIP(gwk::launch_pack_pot(U_[pa_], Ul_[pa_], n_pad_, D_, prec_, 0, packA_[pa_], st_));
     }
     kappa_old_ = kappa_;
+    c_.prof.end(st_);
     // Sinkhorn at eps_t / 8 (Algorithm 3 or 2), warm-started
     for (int k = 0; k < prm_.n_inner; ++k) GW_TRY(inner_iteration(k));
     // covariance: Gamma_{t+1} = sum_ij pi_ij X_i Y_j^T
+    c_.prof.begin(GW_PROF_COVARIANCE, st_);
     GW_TRY(covariance(0, nullptr, rsum_, rm_));
     GW_HIP(gwk::launch_gamma_final(part_, n_, D_, E_, gam_[gcur_], gam64_, gam_[1 - gcur_], scal_, st_));
+    c_.prof.end(st_);
     gcur_ ^= 1;
     ++t_;
     if (t_ >= prm_.n_outer) done_ = true;
@@ -446,6 +526,7 @@ Status Solve::finish(gw_result* out) {
     double* kl64 = ws.get_t<double>(tag_ + "kl64", n_, &st);
     double* c64 = ws.get_t<double>(tag_ + "c64", m_, &st);
     if (!st.good()) return st;
+    c_.prof.begin(GW_PROF_CHECK, st_);
     if (geo_.path == 1) {
         const float kap = (float)kappa_;
         GW_HIP(gwk::launch_check64_direct(D_, X_, xn_, U_[pa_], Ul_[pa_], Zs_, ym_, V_[pb_], Vl_[pb_], kap, n_, m_,
@@ -459,6 +540,8 @@ Status Solve::finish(gw_result* out) {
                                    nullptr, st_));
     }
     GW_HIP(gwk::launch_check_final(r64, kl64, n_, a_, c64, m_, b_, asum_, bsum_, scal_, st_));
+    c_.prof.end(st_);
+    c_.prof.entries = n_ * m_;
     // moments for C(alpha, beta)
     GW_HIP(gwk::launch_moments(X_, n_, D_, a_, mompart_, momx_, st_));
     GW_HIP(gwk::launch_moments(Y_, m_, E_, b_, mompart_, momy_, st_));

@@ -90,7 +90,33 @@ struct SideCfg {
     Landmarks lm;
 };
 
+// Event pairs around kernel launches, resolved on demand.
+class Profiler {
+   public:
+    bool on = false;
+    void begin(int cls, hipStream_t s);
+    void end(hipStream_t s);
+    // resolves recorded pairs into the totals (synchronises the stream)
+    Status collect(hipStream_t s);
+    void reset();
+    ~Profiler();
+    int64_t launches[GW_PROF_CLASSES] = {};
+    double ms[GW_PROF_CLASSES] = {};
+    int64_t entries = 0;
+
+   private:
+    struct Pair {
+        hipEvent_t a, b;
+        int cls;
+    };
+    hipEvent_t take();
+    std::vector<Pair> pairs_;
+    std::vector<hipEvent_t> pool_;
+    Pair cur_{};
+};
+
 struct Ctx {
+    Profiler prof;
     int device = 0;
     hipStream_t stream = nullptr;
     Workspace ws;
@@ -189,4 +215,8 @@ namespace gwr {
 void release_landmarks(Ctx& c);
 Status lift_nystrom(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
                     const std::string& tag);
+}  // namespace gwr
+
+namespace gwr {
+std::vector<int64_t> seeded_landmarks(int64_t n, int nl, uint64_t seed);
 }  // namespace gwr

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import gw_oracle as O
+from workloads import landmark_indices
 
 
 @pytest.mark.parametrize("p", [1.0, 0.5, 1.5, 2.0])
@@ -50,7 +51,7 @@ def test_nystrom_reproduces_landmarks_and_centres():
     rng = np.random.default_rng(23)
     x = rng.standard_normal((300, 3))
     a = rng.dirichlet(np.ones(300))
-    idx = O.choose_landmarks(300, 64, seed=5)
+    idx = landmark_indices(300, 64, seed=5)
     lm = O.fit_landmarks(x[idx], 1.0, 16)
     pix = O.kernel_proj(x[idx], lm)
     assert np.abs(pix - lm.vec * np.sqrt(lm.lam)[None, :]).max() < 1e-10
@@ -78,7 +79,7 @@ def test_jacobian_matches_finite_differences():
 
 
 def test_landmark_choice_is_seeded_prefix():
-    idx = O.choose_landmarks(1000, 50, seed=3)
+    idx = landmark_indices(1000, 50, seed=3)
     want = np.sort(np.random.default_rng(3).permutation(1000)[:50])
     assert np.array_equal(idx, want)
-    assert np.array_equal(O.choose_landmarks(10, 50, seed=3), np.arange(10))
+    assert np.array_equal(landmark_indices(10, 50, seed=3), np.arange(10))

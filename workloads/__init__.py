@@ -16,4 +16,5 @@ from .synth import (  # noqa: F401
     config5_grad,
     subsample,
     rotated_copy,
+    landmark_indices,
 )

@@ -159,6 +159,14 @@ def config5_grad(rep: int = 0, n: int = 50_000, m: int = 30_000,
                    f"grad-{n}x{m}-d16")
 
 
+def landmark_indices(n: int, n_landmarks: int, seed: int) -> np.ndarray:
+    """Landmark subset for kernel PCA: the first n_l entries of a seeded
+    permutation, sorted.  A random draw of the method, so both the oracle and
+    the GPU path receive it as an input."""
+    perm = np.random.default_rng(seed).permutation(n)
+    return np.sort(perm[: min(n_landmarks, n)])
+
+
 def subsample(prob: Problem, k_src: int, k_tgt: int, seed: int) -> Problem:
     """Seeded subsample of both clouds; weights renormalised to sum 1."""
     rng = np.random.default_rng(seed)
