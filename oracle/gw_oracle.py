@@ -459,14 +459,15 @@ def grad_positions_quartic(x, a, pi, cy, p=2.0):
     return 4.0 * np.einsum("ik,ik,ikd->id", w, coef, diff)
 
 
-def grad_weights(cx, cy, a, b, pi, eps, n_iter=20000):
+def grad_weights(cx, cy, a, b, pi, eps, max_iter=200000):
     """Weight gradient of GW_eps: by the Lagrangian of the EGW problem the
     derivative along sum(da) = 0 is <F, da>, with F the EOT potential at eps
-    for the linearised cost grad L(pi*) = 2 sum_kl (cX - cY)^2 pi*_kl.
+    for the linearised cost grad L(pi*) = 2 sum_kl (cX - cY)^2 pi*_kl (the
+    potential of the converged problem: Sinkhorn runs to the FP64 floor).
     Returned centred (sum a_i F_i = 0); constants do not matter on the
     simplex."""
     c = full_linearisation(cx, cy, pi)
-    f, g = sinkhorn(a, b, c, eps, n_iter)
+    f, g = sinkhorn_converged(a, b, c, eps, tol=1e-13, max_iter=max_iter)
     return f - a @ f
 
 
