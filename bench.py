@@ -55,7 +55,80 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3000)
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--save-features", default=None,
+                    help="write the lifted features and weights to this .npz after lifting")
+    ap.add_argument("--features", default=None,
+                    help="load lifted features and weights from this .npz instead of lifting (for counter runs, "
+                         "which then make no eigensolver call)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run three plain 256 MiB device copies first, as the scale for HBM byte counters")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-landmarks", type=int, default=512)
+    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of capacity")
     return ap.parse_args()
+
+
+def serve_bench(args, gwm, torch, dev) -> dict:
+    """Serving workload: requests of log-uniform sizes in [1e3, 5e4] per side,
+    d = 2 or 3, |x - x'| lifted to D = 32, eps = 0.01, 20 x 50 iterations.
+    Capacity = all requests submitted at once; then the Poisson trace is
+    replayed at serve_load x capacity through the batching server and through
+    a one-slot server (one request at a time).  Latency = submission to
+    result, lifting included."""
+    import threading
+
+    from workloads import config4_requests
+
+    trace = config4_requests(n_requests=args.serve_requests, lifted_dim=32)
+    t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
+    reqs = [(t(p.x), t(p.a), t(p.y), t(p.b), p) for _, p in trace]
+    arrivals = np.array([a for a, _ in trace])
+    work = float(sum(p.n * p.m * p.n_outer * p.n_inner for _, p in trace))
+    ctx = gwm.Context()
+
+    def submit(srv, k):
+        x, a, y, b, p = reqs[k]
+        return srv.submit(x, a, y, b, p.eps_start, p.eps_end, p.n_outer, p.n_inner, precision=args.serve_precision,
+                          penalty="power", p=1.0, lifted_dim=32, n_landmarks=args.serve_landmarks, seed=7000 + 2 * k)
+
+    def run(slots, gaps):
+        srv = gwm.Server(ctx, max_slots=slots)
+        tickets = [None] * len(reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+
+        def feeder():
+            for k in range(len(reqs)):
+                if gaps is not None:
+                    delay = t0 + gaps[k] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                tickets[k] = submit(srv, k)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        outs = [srv.wait(tk) for tk in tickets]
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([o["latency_s"] for o in outs])
+        return {"solves_per_s": len(reqs) / wall, "wall_s": wall, "entries_per_s": work / wall,
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "max_marginal_err": float(max(o["marginal_err"] for o in outs))}
+
+    cap = run(args.serve_slots, None)
+    rate = args.serve_load * cap["solves_per_s"]
+    gaps = arrivals / rate  # the trace is a unit-rate Poisson process
+    batched = run(args.serve_slots, gaps)
+    single = run(1, gaps)
+    return {"workload": f"{len(reqs)} requests, N, M log-uniform in [1e3, 5e4], d in {{2, 3}}, |x-x'| lifted to "
+                        f"D=32 ({args.serve_landmarks} landmarks), eps 0.01, 20x50, {args.serve_precision}",
+            "capacity_solves_per_s": cap["solves_per_s"], "capacity_entries_per_s": cap["entries_per_s"],
+            "arrival_rate_per_s": rate, "batched": batched, "one_at_a_time": single,
+            "slots": args.serve_slots}
 
 
 def cpu_baseline(prob, n_sample: int, iters: int) -> dict:
@@ -99,17 +172,34 @@ def main():
     t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
     x, a, y, b = t(prob.x), t(prob.a), t(prob.y), t(prob.b)
 
-    # setup (a0): landmark kernel PCA and Nystrom lifting, timed apart
-    lift_ctx = gwm.Context()
-    for side, seed in ((0, 3101), (1, 3102)):
-        lift_ctx.set_penalty(side, "power", p=prob.p, lifted_dim=args.dim, n_landmarks=args.landmarks)
-        lift_ctx.set_landmarks(side, landmark_indices(n if side == 0 else m, args.landmarks, seed))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    X = lift_ctx.lift(0, x, a)
-    Y = lift_ctx.lift(1, y, b)
-    torch.cuda.synchronize()
-    lift_s = time.perf_counter() - t0
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    lift_s = None
+    if args.features:
+        with np.load(args.features) as z:
+            X, Y = t(z["X"]), t(z["Y"])
+            a, b = t(z["a"]), t(z["b"])
+    else:
+        # setup (a0): landmark kernel PCA and Nystrom lifting, timed apart
+        lift_ctx = gwm.Context()
+        for side, seed in ((0, 3101), (1, 3102)):
+            lift_ctx.set_penalty(side, "power", p=prob.p, lifted_dim=args.dim, n_landmarks=args.landmarks)
+            lift_ctx.set_landmarks(side, landmark_indices(n if side == 0 else m, args.landmarks, seed))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = lift_ctx.lift(0, x, a)
+        Y = lift_ctx.lift(1, y, b)
+        torch.cuda.synchronize()
+        lift_s = time.perf_counter() - t0
+        if args.save_features:
+            np.savez(args.save_features, X=X.cpu().numpy(), Y=Y.cpu().numpy(), a=a.cpu().numpy(),
+                     b=b.cpu().numpy())
 
     ctx = gwm.Context()
     ctx.set_penalty(2, "features")
@@ -175,6 +265,8 @@ def main():
             torch.cuda.synchronize()
             cmp[prec] = float(n) * m * args.n_inner / (time.perf_counter() - t1)
         out["compare_entries_per_s_one_outer_step"] = cmp
+    if not args.no_serve:
+        out["serving"] = serve_bench(args, gwm, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, args.cpu_iters)
     print(json.dumps(out), flush=True)

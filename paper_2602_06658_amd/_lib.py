@@ -136,13 +136,17 @@ def load(path: str | None = None):
     if not os.path.exists(p):
         raise RuntimeError(f"libgwmi.so not found at {p}: build it with paper_2602_06658_amd/build.py")
     lib = ctypes.CDLL(p)
+    missing = []
     for name, (res, args) in SIGNATURES.items():
         try:
             fn = getattr(lib, name)
         except AttributeError:
-            continue  # reported by exported_symbols(); calling it raises
+            missing.append(name)
+            continue
         fn.restype = res
         fn.argtypes = args
+    if missing:
+        raise RuntimeError(f"{p} does not export {', '.join(missing)}: rebuild it")
     if path is None:
         _LIB = lib
     return lib

@@ -23,6 +23,9 @@ COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    # MFMA accumulators in ordinary VGPRs: the exp/add epilogue reads them
+    # without a v_accvgpr_read per element
+    "-mllvm", "--amdgpu-mfma-vgpr-form",
 ]
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lamdhip64", "-lpthread"]
 

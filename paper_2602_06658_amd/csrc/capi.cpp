@@ -7,9 +7,6 @@
 using gwr::Ctx;
 using gwr::Status;
 
-struct gw_ctx {
-    Ctx c;
-};
 
 static gw_status ret(gw_ctx* ctx, const Status& s) {
     if (ctx) ctx->c.err = s.good() ? std::string() : s.msg;

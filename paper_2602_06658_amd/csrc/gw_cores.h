@@ -23,6 +23,20 @@ struct CoreBF16 {
 #pragma unroll
         for (int s = 0; s < KS; ++s) a.v[s] = __builtin_bit_cast(bf16x8_t, p[s * 64]);
     }
+    struct B {
+        bf16x8_t v[KS];
+    };
+    __device__ static void load_b(B& b, const uint4* lds, int lane) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) b.v[s] = __builtin_bit_cast(bf16x8_t, lds[s * 64 + lane]);
+    }
+    // s = X Zs^T from register fragments of both operands.
+    __device__ static f32x16_t tile_ab(const A& a, const B& b) {
+        f32x16_t acc = (f32x16_t)0.0f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[s], b.v[s], acc, 0, 0, 0);
+        return acc;
+    }
     // s = X Zs^T: lane l gets column l % 32, rows acc_row(q, l).
     __device__ static f32x16_t tile(const A& a, const uint4* lds, int lane) {
         f32x16_t acc = (f32x16_t)0.0f;
@@ -53,6 +67,21 @@ struct CoreF32 {
         const uint4* p = pack + (size_t)chunk * KG * 64 + lane;
 #pragma unroll
         for (int g = 0; g < KG; ++g) a.v[g] = __builtin_bit_cast(f32x4_t, p[g * 64]);
+    }
+    struct B {
+        f32x4_t v[KG];
+    };
+    __device__ static void load_b(B& b, const uint4* lds, int lane) {
+#pragma unroll
+        for (int g = 0; g < KG; ++g) b.v[g] = __builtin_bit_cast(f32x4_t, lds[g * 64 + lane]);
+    }
+    __device__ static f32x16_t tile_ab(const A& a, const B& b) {
+        f32x16_t acc = (f32x16_t)0.0f;
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[g][e], b.v[g][e], acc, 0, 0, 0);
+        return acc;
     }
     __device__ static f32x16_t tile(const A& a, const uint4* lds, int lane) {
         f32x16_t acc = (f32x16_t)0.0f;
@@ -86,23 +115,25 @@ __device__ __forceinline__ bool should_run(const int* ctl, int run_if) {
 
 // Cooperative copy of one 32-column chunk of the B pack into LDS, staged
 // through registers so the load of chunk c+1 overlaps the compute of c.
+// Every thread moves FULL units; the first REM threads move one more.  The
+// registers are separate scalars so none of them is demoted to scratch.
 template <int NU>
 struct ChunkStage {
-    static constexpr int PER = (NU + THREADS - 1) / THREADS;
-    uint4 r[PER];
-    __device__ void load(const uint4* src, int tid) {
+    using v4 = unsigned __attribute__((ext_vector_type(4)));
+    static constexpr int FULL = NU / THREADS, REM = NU % THREADS;
+    v4 r[FULL > 0 ? FULL : 1];
+    v4 t;
+    __device__ __forceinline__ void load(const uint4* src_, int tid) {
+        const v4* src = reinterpret_cast<const v4*>(src_);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            int u = tid + k * THREADS;
-            if (u < NU) r[k] = src[u];
-        }
+        for (int k = 0; k < FULL; ++k) r[k] = src[tid + k * THREADS];
+        if (REM > 0 && tid < REM) t = src[FULL * THREADS + tid];
     }
-    __device__ void store(uint4* dst, int tid) const {
+    __device__ __forceinline__ void store(uint4* dst_, int tid) const {
+        v4* dst = reinterpret_cast<v4*>(dst_);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            int u = tid + k * THREADS;
-            if (u < NU) dst[u] = r[k];
-        }
+        for (int k = 0; k < FULL; ++k) dst[tid + k * THREADS] = r[k];
+        if (REM > 0 && tid < REM) dst[FULL * THREADS + tid] = t;
     }
 };
 

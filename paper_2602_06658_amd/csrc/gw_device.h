@@ -20,6 +20,10 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // 2^x on the transcendental unit (v_exp_f32).
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// s_waitcnt vmcnt(0) with expcnt and lgkmcnt left at their maxima (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 
 // Round-to-nearest-even float -> bf16 bits (finite inputs; +-inf kept).
@@ -315,4 +319,20 @@ __device__ __forceinline__ int xcd_remap(int wg, int ntiles) {
     int full = per * X;
     if (wg >= full) return wg;         // ragged tail keeps identity order
     return (wg % X) * per + wg / X;
+}
+
+// Work-group -> (row tile, column tile).  After the XCD remap each XCD walks
+// a contiguous range of a grouped raster: TILE_GROUP row tiles side by side,
+// then the next column tile, so the work-groups resident on one XCD at a time
+// share a few row and column operand blocks in that XCD's L2 instead of each
+// streaming its own row block from HBM.
+constexpr int TILE_GROUP = 8;
+__device__ __forceinline__ void tile_coords(int wg, int n_mt_r, int n_mt_c, int& rb, int& cb) {
+    const int t = xcd_remap(wg, n_mt_r * n_mt_c);
+    const int per_group = TILE_GROUP * n_mt_c;
+    const int grp = t / per_group;
+    const int gsize = min(TILE_GROUP, n_mt_r - grp * TILE_GROUP);
+    const int w = t - grp * per_group;
+    cb = w / gsize;
+    rb = grp * TILE_GROUP + (w - cb * gsize);
 }

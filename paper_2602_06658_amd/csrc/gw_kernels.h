@@ -52,6 +52,17 @@ Geometry pass_geometry(int prec, int d, int64_t n, int64_t m, int multiplier);
 hipError_t launch_pass(const Operands& op, const Geometry& g, const Partials& p, int* ctl,
                        int run_if, int safe, hipStream_t stream);
 
+// The same pass for several independent problems (MFMA path only), one
+// launch per run of consecutive items that share a kernel instantiation
+// (precision class and pack width), at most 16 problems per launch.
+struct PassItem {
+    Operands op;
+    Geometry g;
+    Partials pp;
+    int* ctl;
+};
+hipError_t launch_pass_batch(const PassItem* items, int n, int run_if, int safe, hipStream_t stream);
+
 struct CombineArgs {
     const float* rp;
     const float* rp2;
@@ -77,6 +88,9 @@ struct CombineArgs {
     int is_retry;
 };
 hipError_t launch_combine(const CombineArgs& a, int* ctl, int run_if, hipStream_t stream);
+// Combines of several independent problems, 16 per launch; ctls[r] is the
+// control block of problem r.
+hipError_t launch_combine_batch(const CombineArgs* items, int* const* ctls, int n, int run_if, hipStream_t stream);
 
 // Control block initialisation for a solve: mode, user mode.
 hipError_t launch_ctl_init(int* ctl, int user_mode, hipStream_t stream);

@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(THREADS) k_cov_mfma(CovArgs p) {
     __shared__ float wbuf[2][32 * WS];
     __shared__ float mbuf[2][32];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
-    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    int rb, cb;
+    tile_coords(blockIdx.x, p.n_mt_r, p.n_mt_c, rb, cb);
     const int c0 = cb * p.bc_chunks;
     const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
 
@@ -158,8 +158,8 @@ __global__ void __launch_bounds__(THREADS) k_cov_valu(CovValuArgs p) {
     const int R = D + 3 + p.dw;
     extern __shared__ float zc[];  // [2][32 * R]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
-    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    int rb, cb;
+    tile_coords(blockIdx.x, p.n_mt_r, p.n_mt_c, rb, cb);
     const int c0 = cb * p.bc_chunks;
     const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
     auto load = [&](int buf, int c) {
@@ -237,7 +237,15 @@ __global__ void __launch_bounds__(THREADS) k_cov_valu(CovValuArgs p) {
     }
 }
 
-int cov_tw(int path, int dw) { return path == 1 ? dw : (dw + 31) / 32 * 32; }
+// payload width of the MFMA covariance, in 32-column groups the kernel is
+// instantiated for (1, 2, 3, 4, 6, 8); padded columns carry zeros
+int cov_tw(int path, int dw) {
+    if (path == 1) return dw;
+    int es = (dw + 31) / 32;
+    if (es == 5) es = 6;
+    if (es == 7) es = 8;
+    return es * 32;
+}
 
 int cov_rows_per_group(int path, int prec, int d, int dw) {
     if (path == 1) return COV_VALU_ROWS;
@@ -438,26 +446,38 @@ hipError_t launch_cov_reduce(const CovOut& in, int n_mt_c, int64_t n, int64_t n_
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_gamma_final(const double* part, int nblk, int dx, int dw,
-                                                     const float* gamma_old, double* gamma64, float* gamma32,
+// Sum of the per-block FP64 partials: one thread per output column of the
+// partial table, four strided lanes per column combined in a fixed order.
+__global__ void __launch_bounds__(256) k_gamma_sum(const double* part, int nblk, int width, double* gamma64,
+                                                   float* gamma32, double* scal) {
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, s = threadIdx.x >> 6;
+    const int pidx = blockIdx.x * 64 + c;
+    double acc = 0.0;
+    if (pidx < width + 2)
+        for (int b = s; b < nblk; b += 4) acc += part[(size_t)b * (width + 2) + pidx];
+    red[s][c] = acc;
+    __syncthreads();
+    if (s == 0 && pidx < width + 2) {
+        const double v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        if (pidx < width) {
+            gamma64[pidx] = v;
+            gamma32[pidx] = (float)v;
+        } else {
+            scal[pidx - width] = v;
+        }
+    }
+}
+
+// ||Gamma||^2 and ||Gamma - Gamma_old||^2 in one block, fixed order.
+__global__ void __launch_bounds__(256) k_gamma_norms(const double* gamma64, const float* gamma_old, int width,
                                                      double* scal) {
     __shared__ double s1[256], s2[256];
-    const int width = dx * dw;
     double a1 = 0.0, a2 = 0.0;
-    for (int pidx = threadIdx.x; pidx < width + 2; pidx += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (width + 2) + pidx];
-        if (pidx < width) {
-            gamma64[pidx] = s;
-            gamma32[pidx] = (float)s;
-            const double dlt = s - (double)gamma_old[pidx];
-            a1 += s * s;
-            a2 += dlt * dlt;
-        } else if (pidx == width) {
-            scal[0] = s;
-        } else {
-            scal[1] = s;
-        }
+    for (int p = threadIdx.x; p < width; p += blockDim.x) {
+        const double v = gamma64[p], d = v - (double)gamma_old[p];
+        a1 += v * v;
+        a2 += d * d;
     }
     s1[threadIdx.x] = a1;
     s2[threadIdx.x] = a2;
@@ -478,8 +498,11 @@ __global__ void __launch_bounds__(256) k_gamma_final(const double* part, int nbl
 hipError_t launch_gamma_final(const double* part, int64_t n, int dx, int dw, const float* gamma_old, double* gamma64,
                               float* gamma32, double* scal, hipStream_t stream) {
     const int nblk = (int)((n + RED_ROWS - 1) / RED_ROWS);
-    hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(256), 0, stream, part, nblk, dx, dw, gamma_old, gamma64, gamma32,
-                       scal);
+    const int width = dx * dw;
+    hipLaunchKernelGGL(k_gamma_sum, dim3((width + 2 + 63) / 64), dim3(256), 0, stream, part, nblk, width, gamma64,
+                       gamma32, scal);
+    // gamma_old must not alias gamma32 (the caller double-buffers Gamma)
+    hipLaunchKernelGGL(k_gamma_norms, dim3(1), dim3(256), 0, stream, gamma64, gamma_old, width, scal);
     return hipGetLastError();
 }
 

@@ -47,14 +47,14 @@ struct PassArgs {
 // ---------------------------------------------------------------------------
 
 template <class C, int RW>
-__global__ void __launch_bounds__(THREADS) k_pass_stab(PassArgs p) {
+__device__ __forceinline__ void pass_stab_body(const PassArgs& p, int wg) {
     if (!should_run(p.ctl, p.run_if)) return;
     constexpr int NU = C::UNITS * 64;
     __shared__ uint4 zbuf[2][NU];
     extern __shared__ float dyn[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
-    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    int rb, cb;
+    tile_coords(wg, p.n_mt_r, p.n_mt_c, rb, cb);
     const int c0 = cb * p.bc_chunks;
     const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
     const int bcw = p.bc_chunks * 32;
@@ -82,20 +82,42 @@ __global__ void __launch_bounds__(THREADS) k_pass_stab(PassArgs p) {
 #pragma unroll
                 for (int q = 0; q < 16; ++q) racc[t][q] = 0.f;
             }
+            // complete the row-operand loads here, once per row group, so
+            // the tiles below never wait on the in-flight chunk prefetch
+            wait_vmem_all();
         }
         const bool has_next = it + 1 < total;
         if (has_next) st.load(p.B + (size_t)(c0 + (it + 1) % nch) * NU, tid);
         const uint4* zb = zbuf[it & 1];
-        float cs = 0.f;
+        float cs = -0.0f;  // exact identity for the first add
+        if (act[RW - 1]) {
+            // all row tiles of this wave in range (every wave but the last
+            // one of the last row group): no per-tile branches, the column
+            // fragment is read from LDS once and the tiles interleave
+            typename C::B b;
+            C::load_b(b, zb, lane);
+            f32x16_t s[RW];
 #pragma unroll
-        for (int t = 0; t < RW; ++t) {
-            if (act[t]) {
-                f32x16_t s = C::tile(a[t], zb, lane);
+            for (int t = 0; t < RW; ++t) s[t] = C::tile_ab(a[t], b);
+#pragma unroll
+            for (int t = 0; t < RW; ++t)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    const float e = fast_exp2(s[q]);
+                    const float e = fast_exp2(s[t][q]);
                     racc[t][q] += e;
                     cs += e;
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                if (act[t]) {
+                    f32x16_t s = C::tile(a[t], zb, lane);
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const float e = fast_exp2(s[q]);
+                        racc[t][q] += e;
+                        cs += e;
+                    }
                 }
             }
         }
@@ -122,20 +144,47 @@ __global__ void __launch_bounds__(THREADS) k_pass_stab(PassArgs p) {
     }
 }
 
+
+// Several independent problems in one launch (the serving loop): each
+// work-group finds its problem in the prefix table of work-group counts.
+constexpr int BATCH_MAX = 16;
+struct PassBatch {
+    int n;
+    int start[BATCH_MAX + 1];
+    PassArgs req[BATCH_MAX];
+};
+
+__device__ __forceinline__ int batch_slot(const int* start, int n, int wg) {
+    int r = 0;
+    while (r + 1 < n && wg >= start[r + 1]) ++r;
+    return r;
+}
+
+template <class C, int RW>
+__global__ void __launch_bounds__(THREADS) k_pass_stab(PassArgs p) {
+    pass_stab_body<C, RW>(p, blockIdx.x);
+}
+
+template <class C, int RW>
+__global__ void __launch_bounds__(THREADS) k_pass_stab_batch(PassBatch b) {
+    const int r = batch_slot(b.start, b.n, blockIdx.x);
+    pass_stab_body<C, RW>(b.req[r], blockIdx.x - b.start[r]);
+}
+
 // ---------------------------------------------------------------------------
 // Safe (max-shifted) MFMA pass: per row group, phase 0 finds lane-local row
 // maxima and wave-local column maxima, phase 1 sums 2^{s - max}.
 // ---------------------------------------------------------------------------
 
 template <class C, int RW>
-__global__ void __launch_bounds__(THREADS) k_pass_safe(PassArgs p) {
+__device__ __forceinline__ void pass_safe_body(const PassArgs& p, int wg) {
     if (!should_run(p.ctl, p.run_if)) return;
     constexpr int NU = C::UNITS * 64;
     __shared__ uint4 zbuf[2][NU];
     extern __shared__ float dyn[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
-    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    int rb, cb;
+    tile_coords(wg, p.n_mt_r, p.n_mt_c, rb, cb);
     const int c0 = cb * p.bc_chunks;
     const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
     const int bcw = p.bc_chunks * 32;
@@ -245,6 +294,17 @@ __global__ void __launch_bounds__(THREADS) k_pass_safe(PassArgs p) {
     }
 }
 
+template <class C, int RW>
+__global__ void __launch_bounds__(THREADS) k_pass_safe(PassArgs p) {
+    pass_safe_body<C, RW>(p, blockIdx.x);
+}
+
+template <class C, int RW>
+__global__ void __launch_bounds__(THREADS) k_pass_safe_batch(PassBatch b) {
+    const int r = batch_slot(b.start, b.n, blockIdx.x);
+    pass_safe_body<C, RW>(b.req[r], blockIdx.x - b.start[r]);
+}
+
 // ---------------------------------------------------------------------------
 // VALU pass for D < 16: lane = row (RV rows per lane), columns broadcast
 // from LDS as records [Z_j (D), V_j, m_j].  The exponent is evaluated in the
@@ -301,8 +361,8 @@ __global__ void __launch_bounds__(THREADS) k_pass_valu(ValuArgs p) {
     __shared__ float zc[2][32 * R];
     extern __shared__ float dyn[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = xcd_remap(blockIdx.x, p.n_mt_r * p.n_mt_c);
-    const int rb = tile % p.n_mt_r, cb = tile / p.n_mt_r;
+    int rb, cb;
+    tile_coords(blockIdx.x, p.n_mt_r, p.n_mt_c, rb, cb);
     const int c0 = cb * p.bc_chunks;
     const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
     const int bcw = p.bc_chunks * 32;
@@ -470,6 +530,94 @@ Geometry pass_geometry(int prec, int d, int64_t n, int64_t m, int multiplier) {
     return g;
 }
 
+static PassArgs make_pass_args(const Operands& op, const Geometry& g, const Partials& pp, int* ctl, int run_if) {
+    PassArgs a;
+    a.A = (const uint4*)op.A;
+    a.B = (const uint4*)op.B;
+    a.rp = pp.row;
+    a.rp2 = pp.row2;
+    a.cp = pp.col;
+    a.cp2 = pp.col2;
+    a.ctl = ctl;
+    a.run_if = run_if;
+    a.n_chunks_r = g.n_pad / 32;
+    a.n_chunks_c = g.m_pad / 32;
+    a.rg = g.rg;
+    a.bc_chunks = g.bc_chunks;
+    a.n_mt_r = g.n_mt_r;
+    a.n_mt_c = g.n_mt_c;
+    a.n_pad = g.n_pad;
+    a.m_pad = g.m_pad;
+    return a;
+}
+
+template <class C, int RW>
+static hipError_t launch_mfma_batch(const PassBatch& b, size_t lds, int safe, hipStream_t stream) {
+    if (safe)
+        hipLaunchKernelGGL((k_pass_safe_batch<C, RW>), dim3(b.start[b.n]), dim3(THREADS), lds, stream, b);
+    else
+        hipLaunchKernelGGL((k_pass_stab_batch<C, RW>), dim3(b.start[b.n]), dim3(THREADS), lds, stream, b);
+    return hipGetLastError();
+}
+
+static hipError_t dispatch_batch(int prec, int units, const PassBatch& b, size_t lds, int safe, hipStream_t stream) {
+    if (prec == PREC_F32) {
+        switch (units) {
+            case 3: return launch_mfma_batch<CoreF32<3>, 2>(b, lds, safe, stream);
+            case 5: return launch_mfma_batch<CoreF32<5>, 2>(b, lds, safe, stream);
+            case 7: return launch_mfma_batch<CoreF32<7>, 2>(b, lds, safe, stream);
+            case 9: return launch_mfma_batch<CoreF32<9>, 2>(b, lds, safe, stream);
+            case 13: return launch_mfma_batch<CoreF32<13>, 1>(b, lds, safe, stream);
+            case 17: return launch_mfma_batch<CoreF32<17>, 1>(b, lds, safe, stream);
+            case 25: return launch_mfma_batch<CoreF32<25>, 1>(b, lds, safe, stream);
+            case 33: return launch_mfma_batch<CoreF32<33>, 1>(b, lds, safe, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (units) {
+        case 2: return launch_mfma_batch<CoreBF16<2>, 2>(b, lds, safe, stream);
+        case 3: return launch_mfma_batch<CoreBF16<3>, 2>(b, lds, safe, stream);
+        case 4: return launch_mfma_batch<CoreBF16<4>, 2>(b, lds, safe, stream);
+        case 5: return launch_mfma_batch<CoreBF16<5>, 2>(b, lds, safe, stream);
+        case 7: return launch_mfma_batch<CoreBF16<7>, 2>(b, lds, safe, stream);
+        case 9: return launch_mfma_batch<CoreBF16<9>, 2>(b, lds, safe, stream);
+        case 10: return launch_mfma_batch<CoreBF16<10>, 1>(b, lds, safe, stream);
+        case 13: return launch_mfma_batch<CoreBF16<13>, 1>(b, lds, safe, stream);
+        case 17: return launch_mfma_batch<CoreBF16<17>, 1>(b, lds, safe, stream);
+        case 19: return launch_mfma_batch<CoreBF16<19>, 1>(b, lds, safe, stream);
+        case 25: return launch_mfma_batch<CoreBF16<25>, 1>(b, lds, safe, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass_batch(const PassItem* items, int n, int run_if, int safe, hipStream_t stream) {
+    // consecutive items sharing one kernel instantiation go into one launch
+    int g0 = 0;
+    while (g0 < n) {
+        const int prec = items[g0].op.prec == PREC_F32 ? PREC_F32 : PREC_BF16;
+        const int units = pack_units(items[g0].op.prec, items[g0].op.d);
+        PassBatch b{};
+        b.n = 0;
+        b.start[0] = 0;
+        size_t lds = 0;
+        while (g0 < n && b.n < BATCH_MAX) {
+            const PassItem& it = items[g0];
+            if (it.g.path != 0) return hipErrorInvalidValue;
+            const int p2 = it.op.prec == PREC_F32 ? PREC_F32 : PREC_BF16;
+            if (p2 != prec || pack_units(it.op.prec, it.op.d) != units) break;
+            b.req[b.n] = make_pass_args(it.op, it.g, it.pp, it.ctl, run_if);
+            b.start[b.n + 1] = b.start[b.n] + it.g.n_mt_r * it.g.n_mt_c;
+            const size_t l = (size_t)(safe ? 3 : 1) * WAVES * it.g.bc_chunks * 32 * sizeof(float);
+            lds = l > lds ? l : lds;
+            ++b.n;
+            ++g0;
+        }
+        const hipError_t e = dispatch_batch(prec, units, b, lds, safe, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <class C, int RW>
 static hipError_t launch_mfma(const Operands& op, const Geometry& g, const Partials& pp, int* ctl, int run_if,
                               int safe, hipStream_t stream) {
@@ -590,7 +738,9 @@ struct CombineDev {
     int units;    // pack units per chunk
 };
 
-__global__ void __launch_bounds__(256) k_combine(CombineDev cd, int* ctl, int run_if) {
+// blk / nblk: this block's index among the problem's nblk blocks (the last
+// one to finish takes the mode decision)
+__device__ __forceinline__ void combine_body(const CombineDev& cd, int* ctl, int run_if, int blk, int nblk) {
     const CombineArgs& a = cd.a;
     if (!should_run(ctl, run_if)) return;
     const int mode = ctl[CTL_MODE];
@@ -598,7 +748,7 @@ __global__ void __launch_bounds__(256) k_combine(CombineDev cd, int* ctl, int ru
     const bool safe_parts = a.is_retry || mode == MODE_SAFE;
     const bool check_stab = !a.is_retry && mode == MODE_STAB && user != 2;
     const int nrow = a.do_rows ? a.n : 0;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = blk * blockDim.x + threadIdx.x;
     int bad = 0, unsafe = 0, numeric = 0;
     if (idx < nrow + (a.do_cols ? a.m : 0)) {
         const bool is_row = idx < nrow;
@@ -659,7 +809,7 @@ __global__ void __launch_bounds__(256) k_combine(CombineDev cd, int* ctl, int ru
         if (numeric) atomicOr(&ctl[CTL_NUMERIC], 1);
         __threadfence();
         const int prev = atomicAdd(&ctl[CTL_COUNT], 1);
-        last = prev == (int)gridDim.x - 1;
+        last = prev == nblk - 1;
     }
     __syncthreads();
     if (last && threadIdx.x == 0) {
@@ -679,7 +829,25 @@ __global__ void __launch_bounds__(256) k_combine(CombineDev cd, int* ctl, int ru
     }
 }
 
-hipError_t launch_combine(const CombineArgs& a, int* ctl, int run_if, hipStream_t stream) {
+__global__ void __launch_bounds__(256) k_combine(CombineDev cd, int* ctl, int run_if) {
+    combine_body(cd, ctl, run_if, blockIdx.x, gridDim.x);
+}
+
+struct CombineBatch {
+    int n;
+    int start[BATCH_MAX + 1];
+    int* ctl[BATCH_MAX];
+    CombineDev req[BATCH_MAX];
+};
+static_assert(sizeof(CombineBatch) <= 4000, "batch table must fit the kernel argument space");
+static_assert(sizeof(PassBatch) <= 4000, "batch table must fit the kernel argument space");
+
+__global__ void __launch_bounds__(256) k_combine_batch(CombineBatch b, int run_if) {
+    const int r = batch_slot(b.start, b.n, blockIdx.x);
+    combine_body(b.req[r], b.ctl[r], run_if, blockIdx.x - b.start[r], b.start[r + 1] - b.start[r]);
+}
+
+static CombineDev make_combine_dev(const CombineArgs& a) {
     CombineDev cd;
     cd.a = a;
     cd.kb = 0;
@@ -689,10 +857,35 @@ hipError_t launch_combine(const CombineArgs& a, int* ctl, int run_if, hipStream_
         cd.kb = a.prec == PREC_BF16X3 ? 3 * dp : dp;
         cd.units = pack_units(a.prec, a.d);
     }
+    return cd;
+}
+
+static int combine_blocks(const CombineArgs& a) {
     const int total = (a.do_rows ? a.n : 0) + (a.do_cols ? a.m : 0);
-    const int grid = (total + 255) / 256;
-    hipLaunchKernelGGL(k_combine, dim3(grid), dim3(256), 0, stream, cd, ctl, run_if);
+    return (total + 255) / 256;
+}
+
+hipError_t launch_combine(const CombineArgs& a, int* ctl, int run_if, hipStream_t stream) {
+    const CombineDev cd = make_combine_dev(a);
+    hipLaunchKernelGGL(k_combine, dim3(combine_blocks(a)), dim3(256), 0, stream, cd, ctl, run_if);
     return hipGetLastError();
+}
+
+hipError_t launch_combine_batch(const CombineArgs* items, int* const* ctls, int n, int run_if, hipStream_t stream) {
+    for (int g0 = 0; g0 < n; g0 += BATCH_MAX) {
+        CombineBatch b{};
+        b.n = n - g0 < BATCH_MAX ? n - g0 : BATCH_MAX;
+        b.start[0] = 0;
+        for (int r = 0; r < b.n; ++r) {
+            b.req[r] = make_combine_dev(items[g0 + r]);
+            b.ctl[r] = ctls[g0 + r];
+            b.start[r + 1] = b.start[r] + combine_blocks(items[g0 + r]);
+        }
+        hipLaunchKernelGGL(k_combine_batch, dim3(b.start[b.n]), dim3(256), 0, stream, b, run_if);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 __global__ void k_ctl_init(int* ctl, int user) {

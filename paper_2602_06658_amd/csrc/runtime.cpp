@@ -226,6 +226,53 @@ Status lift_side(Ctx& c, int side, const float* x, int64_t n, int d, const float
 
 static constexpr double LOG2E = 1.4426950408889634;
 
+Status Solve::configure(int64_t n, int dx, int64_t m, int dy, const gw_params& prm) {
+    n_ = n;
+    m_ = m;
+    D_ = feature_dim(c_.side[0], dx);
+    E_ = feature_dim(c_.side[1], dy);
+    if (D_ < 1 || E_ < 1 || D_ > MAX_DIM || E_ > MAX_DIM) return fail(GW_EINVAL, "lifted dimension out of range");
+    prec_ = prm.precision;
+    if (D_ <= VALU_MAX_DIM) prec_ = PREC_F32;  // no contraction worth MFMA
+    if (prec_ == PREC_BF16X3 && D_ > MAX_DIM_BF16X3)
+        return fail(GW_EUNSUPPORTED, "split-BF16 supports D <= 128");
+    n_pad_ = (n + 31) / 32 * 32;
+    m_pad_ = (m + 31) / 32 * 32;
+    geo_ = gwk::pass_geometry(prec_, D_, n, m, 1);
+    if (geo_.path == 1 && E_ > 16)
+        return fail(GW_EUNSUPPORTED, "source dimension below 16 needs a target dimension of at most 16");
+
+    // covariance geometry: one row group per macro tile, few column tiles;
+    // forward (source rows, payload Y) and swapped (target rows, payload X)
+    {
+        const int path = geo_.path;
+        auto geom = [&](int64_t rows_pad, int64_t cols_pad, int dw, int& rg, int& bc, int& mtr, int& mtc, int& tw) {
+            const int rpg = gwk::cov_rows_per_group(path, prec_, D_, dw);
+            rg = 1;
+            mtr = (int)((rows_pad + rpg - 1) / rpg);
+            const int nchc = (int)(cols_pad / 32);
+            tw = gwk::cov_tw(path, dw);
+            int want = std::max(1, (2048 + mtr - 1) / mtr);
+            const size_t per_tile = (size_t)rows_pad * (tw + 2) * sizeof(float);
+            const int mem_cap = (int)std::max<size_t>(1, ((size_t)1 << 30) / per_tile);
+            want = std::min(want, std::min(mem_cap, nchc));
+            bc = (nchc + want - 1) / want;
+            mtc = (nchc + bc - 1) / bc;
+        };
+        geom(n_pad_, m_pad_, E_, cov_rg_, cov_bc_, cov_mtr_, cov_mtc_, cov_tw_);
+        geom(m_pad_, n_pad_, D_, cov2_rg_, cov2_bc_, cov2_mtr_, cov2_mtc_, cov2_tw_);
+    }
+    return Status::ok();
+}
+
+size_t Solve::plan_bytes(Ctx& c, int64_t n, int dx, int64_t m, int dy, const gw_params& prm) {
+    Solve s(c, "plan.");
+    s.prm_ = prm;
+    if (!s.configure(n, dx, m, dy, prm).good()) return 0;
+    if (!s.buffers(true).good()) return 0;
+    return s.footprint_;
+}
+
 Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
                     const float* b, const gw_params& prm, const float* gamma0, const float* f0, const float* g0,
                     int pen_src, int pen_tgt, hipStream_t stream) {
@@ -241,32 +288,7 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
     b_ = b;
     pen_[0] = pen_src;
     pen_[1] = pen_tgt;
-    D_ = feature_dim(c_.side[0], dx);
-    E_ = feature_dim(c_.side[1], dy);
-    if (D_ < 1 || E_ < 1 || D_ > MAX_DIM || E_ > MAX_DIM) return fail(GW_EINVAL, "lifted dimension out of range");
-    prec_ = prm.precision;
-    if (D_ <= VALU_MAX_DIM) prec_ = PREC_F32;  // no contraction worth MFMA
-    if (prec_ == PREC_BF16X3 && D_ > MAX_DIM_BF16X3)
-        return fail(GW_EUNSUPPORTED, "split-BF16 supports D <= 128");
-    n_pad_ = (n + 31) / 32 * 32;
-    m_pad_ = (m + 31) / 32 * 32;
-    geo_ = gwk::pass_geometry(prec_, D_, n, m, 1);
-
-    // covariance geometry: one row group per macro tile, few column tiles
-    {
-        const int path = geo_.path;
-        const int rpg = gwk::cov_rows_per_group(path, prec_, D_, E_);
-        cov_rg_ = 1;
-        cov_mtr_ = (int)((n_pad_ + rpg - 1) / rpg);
-        const int nchc = (int)(m_pad_ / 32);
-        cov_tw_ = gwk::cov_tw(path, E_);
-        int want = std::max(1, (2048 + cov_mtr_ - 1) / cov_mtr_);
-        const size_t per_tile = (size_t)n_pad_ * (cov_tw_ + 2) * sizeof(float);
-        const int mem_cap = (int)std::max<size_t>(1, ((size_t)1 << 30) / per_tile);
-        want = std::min(want, std::min(mem_cap, nchc));
-        cov_bc_ = (nchc + want - 1) / want;
-        cov_mtc_ = (nchc + cov_bc_ - 1) / cov_bc_;
-    }
+    GW_TRY(configure(n, dx, m, dy, prm));
     GW_TRY(buffers());
 
     // weights: validation also gives their FP64 sums
@@ -329,18 +351,18 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
     return Status::ok();
 }
 
-Status Solve::buffers() {
+Status Solve::buffers(bool dry) {
     Status st;
     auto& ws = c_.ws;
     const std::string& T = tag_;
     footprint_ = 0;
     auto getf = [&](const char* nm, size_t cnt) -> float* {
         footprint_ += cnt * 4;
-        return ws.get_t<float>(T + nm, cnt, &st);
+        return dry ? nullptr : ws.get_t<float>(T + nm, cnt, &st);
     };
     auto getd = [&](const char* nm, size_t cnt) -> double* {
         footprint_ += cnt * 8;
-        return ws.get_t<double>(T + nm, cnt, &st);
+        return dry ? nullptr : ws.get_t<double>(T + nm, cnt, &st);
     };
     X_ = getf("X", (size_t)n_pad_ * D_);
     Y_ = getf("Y", (size_t)m_pad_ * E_);
@@ -373,12 +395,13 @@ Status Solve::buffers() {
     rp2_ = getf("rp2", (size_t)geo_.n_mt_c * n_pad_);
     cp_ = getf("cp", (size_t)geo_.n_mt_r * m_pad_);
     cp2_ = getf("cp2", (size_t)geo_.n_mt_r * m_pad_);
-    const int tw_max = std::max(gwk::cov_tw(geo_.path, E_), gwk::cov_tw(geo_.path, D_));
-    const int mtc_max = cov_mtc_;
+    // partial sums of the covariance pass in either direction
+    const size_t tp_n = std::max((size_t)cov_mtc_ * n_pad_ * cov_tw_, (size_t)cov2_mtc_ * m_pad_ * cov2_tw_);
+    const size_t cr_n = std::max((size_t)cov_mtc_ * n_pad_, (size_t)cov2_mtc_ * m_pad_);
     const int64_t np_max = std::max(n_pad_, m_pad_);
-    Tp_ = getf("Tp", (size_t)mtc_max * np_max * tw_max);
-    crp_ = getf("crp", (size_t)mtc_max * np_max);
-    crmp_ = getf("crmp", (size_t)mtc_max * np_max);
+    Tp_ = getf("Tp", tp_n);
+    crp_ = getf("crp", cr_n);
+    crmp_ = getf("crmp", cr_n);
     rsum_ = getf("rsum", np_max);
     rm_ = getf("rm", np_max);
     part_ = getd("part", std::max(gwk::cov_reduce_part_doubles(n_, D_, E_), gwk::cov_reduce_part_doubles(m_, E_, D_)));
@@ -390,59 +413,65 @@ Status Solve::buffers() {
     return st;
 }
 
-Status Solve::inner_iteration(int k) {
-    (void)k;
-    gwk::Operands op{};
+void Solve::make_half(int do_rows, int do_cols, float step, gwk::Operands& op, gwk::CombineArgs& ca) {
+    op = gwk::Operands{};
     op.prec = prec_;
     op.d = D_;
+    if (geo_.path == 0) {
+        op.A = packA_[pa_];
+        op.B = packB_[pb_];
+    } else {
+        op.X = X_;
+        op.xn = xn_;
+        op.U = U_[pa_];
+        op.Ul = Ul_[pa_];
+        op.Zs = Zs_;
+        op.ms = ym_;
+        op.V = V_[pb_];
+        op.Vl = Vl_[pb_];
+        op.kappa = (float)kappa_;
+    }
+    ca = gwk::CombineArgs{};
+    ca.rp = rp_;
+    ca.rp2 = rp2_;
+    ca.cp = cp_;
+    ca.cp2 = cp2_;
+    ca.n_mt_c = geo_.n_mt_c;
+    ca.n_mt_r = geo_.n_mt_r;
+    ca.n = (int)n_;
+    ca.m = (int)m_;
+    ca.n_pad = (int)n_pad_;
+    ca.m_pad = (int)m_pad_;
+    ca.la2 = la2_;
+    ca.lb2 = lb2_;
+    ca.U_cur = U_[pa_];
+    ca.Ul_cur = Ul_[pa_];
+    ca.V_cur = V_[pb_];
+    ca.Vl_cur = Vl_[pb_];
+    ca.U_next = U_[1 - pa_];
+    ca.Ul_next = Ul_[1 - pa_];
+    ca.V_next = V_[1 - pb_];
+    ca.Vl_next = Vl_[1 - pb_];
+    ca.packA_next = geo_.path == 0 && do_rows ? packA_[1 - pa_] : nullptr;
+    ca.packB_next = geo_.path == 0 && do_cols ? packB_[1 - pb_] : nullptr;
+    ca.prec = prec_;
+    ca.d = D_;
+    ca.do_rows = do_rows;
+    ca.do_cols = do_cols;
+    ca.step = step;
+    ca.is_retry = 0;
+}
+
+Status Solve::inner_iteration(int k) {
+    (void)k;
     gwk::Partials pp{rp_, rp2_, cp_, cp2_};
-    auto set_ops = [&]() {
-        if (geo_.path == 0) {
-            op.A = packA_[pa_];
-            op.B = packB_[pb_];
-        } else {
-            op.X = X_;
-            op.xn = xn_;
-            op.U = U_[pa_];
-            op.Ul = Ul_[pa_];
-            op.Zs = Zs_;
-            op.ms = ym_;
-            op.V = V_[pb_];
-            op.Vl = Vl_[pb_];
-            op.kappa = (float)kappa_;
-        }
-    };
+    // one half-step: stabilised pass (runs in stabilised mode), safe pass
+    // (runs in safe mode), combine; if the combine flagged the stabilised
+    // sums, the safe pass and a combine run again as the retry
     auto half = [&](int do_rows, int do_cols, float step) -> Status {
-        set_ops();
-        gwk::CombineArgs ca{};
-        ca.rp = rp_;
-        ca.rp2 = rp2_;
-        ca.cp = cp_;
-        ca.cp2 = cp2_;
-        ca.n_mt_c = geo_.n_mt_c;
-        ca.n_mt_r = geo_.n_mt_r;
-        ca.n = (int)n_;
-        ca.m = (int)m_;
-        ca.n_pad = (int)n_pad_;
-        ca.m_pad = (int)m_pad_;
-        ca.la2 = la2_;
-        ca.lb2 = lb2_;
-        ca.U_cur = U_[pa_];
-        ca.Ul_cur = Ul_[pa_];
-        ca.V_cur = V_[pb_];
-        ca.Vl_cur = Vl_[pb_];
-        ca.U_next = U_[1 - pa_];
-        ca.Ul_next = Ul_[1 - pa_];
-        ca.V_next = V_[1 - pb_];
-        ca.Vl_next = Vl_[1 - pb_];
-        ca.packA_next = geo_.path == 0 && do_rows ? packA_[1 - pa_] : nullptr;
-        ca.packB_next = geo_.path == 0 && do_cols ? packB_[1 - pb_] : nullptr;
-        ca.prec = prec_;
-        ca.d = D_;
-        ca.do_rows = do_rows;
-        ca.do_cols = do_cols;
-        ca.step = step;
-        ca.is_retry = 0;
+        gwk::Operands op;
+        gwk::CombineArgs ca;
+        make_half(do_rows, do_cols, step, op, ca);
         GW_PROF(GW_PROF_PASS_STAB, gwk::launch_pass(op, geo_, pp, ctl_, RUN_STAB, 0, st_));
         GW_PROF(GW_PROF_PASS_SAFE, gwk::launch_pass(op, geo_, pp, ctl_, RUN_SAFE, 1, st_));
         GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_ALWAYS, st_));
@@ -465,6 +494,16 @@ Status Solve::inner_iteration(int k) {
     return Status::ok();
 }
 
+void Solve::iteration_items(gwk::PassItem& item, gwk::CombineArgs& main, gwk::CombineArgs& retry, int** ctl) {
+    make_half(1, 1, 0.5f, item.op, main);
+    item.g = geo_;
+    item.pp = gwk::Partials{rp_, rp2_, cp_, cp2_};
+    item.ctl = ctl_;
+    retry = main;
+    retry.is_retry = 1;
+    *ctl = ctl_;
+}
+
 Status Solve::covariance(int rows_side, float* T_out, float* r_out, float* rm_out) {
     gwk::CovOut out{Tp_, crp_, crmp_, 0};
     if (rows_side == 0) {
@@ -475,11 +514,27 @@ Status Solve::covariance(int rows_side, float* T_out, float* r_out, float* rm_ou
         GW_HIP(gwk::launch_cov_reduce(out, cov_mtc_, n_, n_pad_, X_, D_, xn_, E_, T_out, r_out, rm_out, part_, st_));
         return Status::ok();
     }
-    return fail(GW_EUNSUPPORTED, "column-side covariance is issued by the gradient path");
+    // target rows, source columns: the exponent is symmetric in the two
+    // operands (s_ij = sum_k A_ik B_jk, or the direct form with X <-> Z,
+    // n <-> m, U <-> V), so the same kernels run with the packs swapped and
+    // X as the payload; gives T'_j = sum_i pi_ij X_i and sum_i pi_ij |X_i|^2
+    out.tw = cov2_tw_;
+    GW_HIP(gwk::launch_cov(geo_.path, prec_, D_, packB_[pb_], packA_[pa_], Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_,
+                           U_[pa_], Ul_[pa_], (float)kappa_, X_, xn_, D_, m_pad_, n_pad_, cov2_rg_, cov2_bc_,
+                           cov2_mtr_, cov2_mtc_, out, st_));
+    GW_HIP(gwk::launch_cov_reduce(out, cov2_mtc_, m_, m_pad_, Y_, E_, ym_, D_, T_out, r_out, rm_out, part_, st_));
+    return Status::ok();
 }
 
 Status Solve::outer_step() {
     if (done_) return Status::ok();
+    GW_TRY(begin_outer());
+    // Sinkhorn at eps_t / 8 (Algorithm 3 or 2), warm-started
+    for (int k = 0; k < prm_.n_inner; ++k) GW_TRY(inner_iteration(k));
+    return end_outer();
+}
+
+Status Solve::begin_outer() {
     const int t = t_;
     eps_t_ = eps_sched_[t];
     kappa_ = LOG2E * 8.0 / eps_t_;
@@ -499,8 +554,10 @@ Status Solve::outer_step() {
     }
     kappa_old_ = kappa_;
     c_.prof.end(st_);
-    // Sinkhorn at eps_t / 8 (Algorithm 3 or 2), warm-started
-    for (int k = 0; k < prm_.n_inner; ++k) GW_TRY(inner_iteration(k));
+    return Status::ok();
+}
+
+Status Solve::end_outer() {
     // covariance: Gamma_{t+1} = sum_ij pi_ij X_i Y_j^T
     c_.prof.begin(GW_PROF_COVARIANCE, st_);
     GW_TRY(covariance(0, nullptr, rsum_, rm_));

@@ -153,15 +153,36 @@ class Solve {
     Status finish(gw_result* out);
     // Gradients of the final state (after finish).
     Status gradients(float* grad_x, float* grad_a, float* grad_y, float* grad_b);
+
+    // Stepwise control (serving loop): outer_step() is begin_outer(),
+    // n_inner inner_iteration() calls, end_outer().
+    Status begin_outer();
+    Status inner_iteration(int k);
+    Status end_outer();
+    // Symmetric MFMA-path solves can run their Sinkhorn iterations in the
+    // batched kernels: the arguments of the current iteration, then
+    // advance_parity() once it is enqueued.
+    bool batchable() const { return geo_.path == 0 && prm_.symmetric != 0; }
+    void iteration_items(gwk::PassItem& item, gwk::CombineArgs& main, gwk::CombineArgs& retry, int** ctl);
+    void advance_parity() {
+        pa_ ^= 1;
+        pb_ ^= 1;
+    }
+    int n_inner() const { return prm_.n_inner; }
+    // Device bytes of the solve's buffers for these sizes (nothing allocated);
+    // 0 if the sizes are rejected.
+    static size_t plan_bytes(Ctx& c, int64_t n, int dx, int64_t m, int dy, const gw_params& prm);
     size_t footprint() const { return footprint_; }
     int64_t n() const { return n_; }
     int64_t m() const { return m_; }
     double entries_per_outer() const { return (double)n_ * (double)m_ * prm_.n_inner; }
 
    private:
-    Status buffers();
-    Status inner_iteration(int k);
+    Status configure(int64_t n, int dx, int64_t m, int dy, const gw_params& prm);
+    Status buffers(bool dry = false);
+    void make_half(int do_rows, int do_cols, float step, gwk::Operands& op, gwk::CombineArgs& ca);
     Status covariance(int rows_side, float* T_out, float* r_out, float* rm_out);
+    Status side_gradient(int side, float* grad_pos, float* grad_w);
 
     Ctx& c_;
     std::string tag_;
@@ -177,6 +198,8 @@ class Solve {
     const float* b_ = nullptr;
     gwk::Geometry geo_{};
     int cov_rg_ = 1, cov_bc_ = 1, cov_mtr_ = 1, cov_mtc_ = 1;
+    // covariance with the target as the row operand (gradient of the target)
+    int cov2_rg_ = 1, cov2_bc_ = 1, cov2_mtr_ = 1, cov2_mtc_ = 1, cov2_tw_ = 0;
     int t_ = 0;
     bool done_ = false;
     int pa_ = 0, pb_ = 0;      // pack / potential parities
@@ -210,6 +233,11 @@ class Solve {
 };
 
 }  // namespace gwr
+
+// The opaque handle of the C ABI.
+struct gw_ctx {
+    gwr::Ctx c;
+};
 
 namespace gwr {
 void release_landmarks(Ctx& c);

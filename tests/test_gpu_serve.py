@@ -1,0 +1,100 @@
+"""Serving loop (gw_server_* through the C ABI): continuous batching of
+uneven requests on one GPU.
+
+* Each result is the same alone and in the mix: a request solved by
+  gw_solve by itself and the same request served among others of different
+  sizes give identical potentials, Gamma and loss (the batched launches run
+  the same per-problem work; compared bit for bit).
+* Admission respects the slot count and the HBM budget; a request larger
+  than the budget is rejected; a queued request can be cancelled.
+"""
+import numpy as np
+import pytest
+import torch
+
+from workloads import config4_requests
+
+pytestmark = pytest.mark.gpu
+
+D = 32
+
+
+def dev(v):
+    return torch.tensor(np.asarray(v, dtype=np.float32), device="cuda")
+
+
+def _requests(k, lo=600, hi=3000, seed=4100):
+    """k requests shaped like the serving workload, smaller sizes."""
+    reqs = config4_requests(n_requests=k, lo=lo, hi=hi, lifted_dim=D, seed_base=seed)
+    return [(dev(p.x), dev(p.a), dev(p.y), dev(p.b), p) for _, p in reqs]
+
+
+def _alone(gw, x, a, y, b, prob, seed, **kw):
+    ctx = gw.Context()
+    ctx.set_penalty(0, "power", p=1.0, lifted_dim=D, n_landmarks=256, seed=seed)
+    ctx.set_penalty(1, "power", p=1.0, lifted_dim=D, n_landmarks=256, seed=seed + 1)
+    return ctx.solve(x, a, y, b, prob.eps_start, prob.eps_end, kw.get("n_outer", 4), kw.get("n_inner", 30),
+                     precision=kw.get("precision", "fp32"))
+
+
+def _submit(srv, x, a, y, b, prob, seed, **kw):
+    return srv.submit(x, a, y, b, prob.eps_start, prob.eps_end, kw.get("n_outer", 4), kw.get("n_inner", 30),
+                      precision=kw.get("precision", "fp32"), penalty="power", p=1.0, lifted_dim=D,
+                      n_landmarks=256, seed=seed)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_alone_equals_mix(gw, prec):
+    reqs = _requests(7)
+    alone = [_alone(gw, *r, seed=100 + i, precision=prec) for i, r in enumerate(reqs)]
+    ctx = gw.Context()
+    srv = gw.Server(ctx, max_slots=3)
+    tickets = [_submit(srv, *r, seed=100 + i, precision=prec) for i, r in enumerate(reqs)]
+    mixed = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    print("stats", st)
+    assert st["completed"] == len(reqs)
+    for i, (al, mx) in enumerate(zip(alone, mixed)):
+        sizes = (reqs[i][0].shape[0], reqs[i][2].shape[0])
+        same = all(torch.equal(al[k], mx[k]) for k in ("f", "g", "gamma"))
+        print(i, sizes, "loss", al["loss_lift"], mx["loss_lift"], "bitwise", same, "latency", mx["latency_s"])
+        assert same
+        assert al["loss_lift"] == mx["loss_lift"]
+        assert al["marginal_err"] == mx["marginal_err"]
+
+
+def test_budget_admission_and_rejection(gw):
+    reqs = _requests(4, lo=1000, hi=1500, seed=4200)
+    ctx = gw.Context()
+    probe = gw.Server(ctx, max_slots=8)
+    t0 = _submit(probe, *reqs[0], seed=7)
+    probe.wait(t0)
+    probe.close()
+    # a budget below any single request rejects it at submission
+    tiny = gw.Server(ctx, max_slots=8, hbm_budget_bytes=1 << 20)
+    with pytest.raises(gw.GWError):
+        _submit(tiny, *reqs[0], seed=7)
+    assert tiny.stats()["rejected"] == 1
+    tiny.close()
+    # a budget that holds about one request at a time still completes all
+    srv = gw.Server(ctx, max_slots=8, hbm_budget_bytes=96 << 20)
+    tickets = [_submit(srv, *r, seed=20 + i) for i, r in enumerate(reqs)]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert all(np.isfinite(o["loss_lift"]) for o in outs)
+
+
+def test_cancel_queued(gw):
+    reqs = _requests(3, lo=2000, hi=2500, seed=4300)
+    ctx = gw.Context()
+    srv = gw.Server(ctx, max_slots=1)
+    tickets = [_submit(srv, *r, seed=30 + i, n_outer=6, n_inner=60) for i, r in enumerate(reqs)]
+    srv.cancel(tickets[2])
+    with pytest.raises(gw.GWError) as ei:
+        srv.wait(tickets[2])
+    assert "CANCELLED" in str(ei.value)
+    assert np.isfinite(srv.wait(tickets[0])["loss_lift"])
+    assert np.isfinite(srv.wait(tickets[1])["loss_lift"])
+    assert srv.stats()["cancelled"] == 1
+    srv.close()

@@ -17,4 +17,5 @@ from .synth import (  # noqa: F401
     subsample,
     rotated_copy,
     landmark_indices,
+    grad_points,
 )

@@ -159,6 +159,21 @@ def config5_grad(rep: int = 0, n: int = 50_000, m: int = 30_000,
                    f"grad-{n}x{m}-d16")
 
 
+def grad_points(seed: int, n: int, m: int, d: int, noise: float = 0.05, scale: float = 1.0):
+    """Small gradient-parity inputs: x ~ N(0, scale^2 I_d); y = an orthogonal
+    image of a random subset of x plus N(0, noise^2) noise; weights
+    Dirichlet(3), rounded to float32 and renormalised in float64.  Returns
+    float32-representable float64 arrays (x, a, y, b)."""
+    rng = np.random.default_rng(seed)
+    x = scale * rng.standard_normal((n, d))
+    q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    y = x[rng.choice(n, m, replace=False)] @ q + noise * rng.standard_normal((m, d))
+    f32 = lambda v: np.asarray(v, dtype=np.float32).astype(np.float64)  # noqa: E731
+    a = f32(rng.dirichlet(np.ones(n) * 3))
+    b = f32(rng.dirichlet(np.ones(m) * 3))
+    return f32(x), a / a.sum(), f32(y), b / b.sum()
+
+
 def landmark_indices(n: int, n_landmarks: int, seed: int) -> np.ndarray:
     """Landmark subset for kernel PCA: the first n_l entries of a seeded
     permutation, sorted.  A random draw of the method, so both the oracle and
