@@ -51,11 +51,19 @@ int cov_tw(int path, int dw);
 int cov_rows_per_group(int path, int prec, int d, int dw);
 // VALU path (path 1): direct form with X/xn/U rows, Zs = Z/ms = |Y|^2/V
 // columns and kappa; mw is ignored there (the column norm is the weight).
-hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, const float* X, const float* xn,
-                      const float* U, const float* Ul, const float* Zs, const float* ms, const float* V,
-                      const float* Vl, float kappa, const float* W, const float* mw, int dw, int64_t n_pad,
-                      int64_t m_pad, int rg, int bc_chunks, int n_mt_r, int n_mt_c, const CovOut& out,
-                      hipStream_t stream);
+// PW: payload pack (launch_pack_payload of W) when cov_bf16_form holds, else
+// unused.
+hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, const void* PW, const float* X,
+                      const float* xn, const float* U, const float* Ul, const float* Zs, const float* ms,
+                      const float* V, const float* Vl, float kappa, const float* W, const float* mw, int dw,
+                      int64_t n_pad, int64_t m_pad, int rg, int bc_chunks, int n_mt_r, int n_mt_c,
+                      const CovOut& out, hipStream_t stream);
+// The BF16 precision form's covariance (pi and payload split into BF16
+// hi/lo pairs) applies to these shapes; its payload pack is built once per
+// solve from the row-major payload W (m x dw).
+bool cov_bf16_form(int path, int prec, int d, int dw);
+size_t payload_pack_bytes(int64_t rows_pad, int dw);
+hipError_t launch_pack_payload(const float* W, int64_t m, int64_t m_pad, int dw, void* out, hipStream_t stream);
 
 // Reduce the covariance partials: T (n x dw, optional), r, rm (optional),
 // Gamma partials Xs^T T in FP64 and scalar partials [sum r, sum xs_norm rm].

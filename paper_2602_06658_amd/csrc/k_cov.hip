@@ -17,6 +17,7 @@ namespace gwk {
 struct CovArgs {
     const uint4* A;     // row-side pack
     const uint4* B;     // column-side pack
+    const uint4* PW;    // BF16 form: payload pack (see k_pack_payload), else unused
     const float* W;     // column-side features, m_pad x dw
     const float* mw;    // column-side norms
     int dw;
@@ -122,6 +123,172 @@ __global__ void __launch_bounds__(THREADS) k_cov_mfma(CovArgs p) {
         if (has_next) {
             st.store(zbuf[(it + 1) & 1], tid);
             load_w((it + 1) & 1, cn);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Covariance of the BF16 precision form: pi and the payload W split into BF16
+// (hi, lo) pairs, T accumulated from hi*hi + hi*lo + lo*hi on BF16 MFMA with
+// FP32 accumulators (relative error of each product ~2^-17 instead of the
+// 2^-9 of plain BF16; the lo*lo term, ~2^-18, is dropped).
+//
+// The exponent tile in transposed form leaves lane l with pi[i = l%32][j]
+// for j = acc_row(q, l), q = 0..15.  Taking q = 8 kb + e (e = 0..7) as the
+// k slots of block kb makes those eight values the lane's A fragment as they
+// are, provided the payload is packed with the same j order:
+//   slot (kb, h = l/32, e) <-> j = 16 kb + (e < 4 ? 4h + e : 4 + 4h + e).
+// Payload pack: [chunk of 32 j][es][kb][hi, lo][lane 64][8 bf16], lane l
+// holding W[32 chunk + j(kb, l/32, e)][32 es + l%32] (zero outside).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int pw_j(int kb, int h, int e) { return 16 * kb + (e < 4 ? 4 * h + e : 4 + 4 * h + e); }
+
+__global__ void __launch_bounds__(256) k_pack_payload(const float* W, int64_t m, int dw, int es_n, int64_t n_chunks,
+                                                     uint16_t* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_chunks * es_n * 2 * 64) return;
+    const int lane = (int)(t & 63);
+    int64_t r = t >> 6;
+    const int kb = (int)(r & 1);
+    r >>= 1;
+    const int es = (int)(r % es_n);
+    const int64_t c = r / es_n;
+    const int h = lane >> 5, col = es * 32 + (lane & 31);
+    uint16_t* base = out + ((((size_t)c * es_n + es) * 2 + kb) * 2) * 64 * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t j = c * 32 + pw_j(kb, h, e);
+        const float v = (j < m && col < dw) ? W[j * dw + col] : 0.f;
+        const uint16_t hi = f32_to_bf16_bits(v);
+        base[lane * 8 + e] = hi;
+        base[64 * 8 + lane * 8 + e] = f32_to_bf16_bits(v - bf16_bits_to_f32(hi));
+    }
+}
+
+size_t payload_pack_bytes(int64_t rows_pad, int dw) {
+    const int es_n = cov_tw(0, dw) / 32;
+    return (size_t)(rows_pad / 32) * es_n * 2 * 2 * 64 * 16;
+}
+
+hipError_t launch_pack_payload(const float* W, int64_t m, int64_t m_pad, int dw, void* out, hipStream_t stream) {
+    const int es_n = cov_tw(0, dw) / 32;
+    const int64_t n_chunks = m_pad / 32;
+    const int64_t total = n_chunks * es_n * 2 * 64;
+    hipLaunchKernelGGL(k_pack_payload, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, W, m, dw, es_n,
+                       n_chunks, (uint16_t*)out);
+    return hipGetLastError();
+}
+
+template <int KS, int RW, int ES>
+__global__ void __launch_bounds__(THREADS) k_cov_bf16(CovArgs p) {
+    using C = CoreBF16<KS>;
+    constexpr int NU = KS * 64;
+    constexpr int NW = ES * 2 * 2 * 64;
+    __shared__ uint4 zbuf[2][NU];
+    __shared__ uint4 wbuf[2][NW];
+    __shared__ float mbuf[2][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int rb, cb;
+    tile_coords(blockIdx.x, p.n_mt_r, p.n_mt_c, rb, cb);
+    const int c0 = cb * p.bc_chunks;
+    const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
+
+    ChunkStage<NU> st;
+    ChunkStage<NW> sw;
+    float mnext = 0.f;
+    st.load(p.B + (size_t)c0 * NU, tid);
+    sw.load(p.PW + (size_t)c0 * NW, tid);
+    if (tid < 32) mnext = p.mw[c0 * 32 + tid];
+    st.store(zbuf[0], tid);
+    sw.store(wbuf[0], tid);
+    if (tid < 32) mbuf[0][tid] = mnext;
+    __syncthreads();
+
+    typename C::A a[RW];
+    f32x16_t tacc[RW][ES];
+    float r[RW], rm[RW];
+    bool act[RW];
+    int rchunk0 = 0;
+    const int total = p.rg * nch;
+    for (int it = 0; it < total; ++it) {
+        const int g = it / nch, cc = it - g * nch;
+        if (cc == 0) {
+            rchunk0 = (rb * p.rg + g) * (WAVES * RW) + wave * RW;
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                act[t] = rchunk0 + t < p.n_chunks_r;
+                if (act[t]) C::load(a[t], p.A, rchunk0 + t, lane);
+#pragma unroll
+                for (int es = 0; es < ES; ++es) tacc[t][es] = (f32x16_t)0.0f;
+                r[t] = 0.f;
+                rm[t] = 0.f;
+            }
+            wait_vmem_all();
+        }
+        const bool has_next = it + 1 < total;
+        const int cn = c0 + (it + 1) % nch;
+        if (has_next) {
+            st.load(p.B + (size_t)cn * NU, tid);
+            sw.load(p.PW + (size_t)cn * NW, tid);
+            if (tid < 32) mnext = p.mw[cn * 32 + tid];
+        }
+        const uint4* zb = zbuf[it & 1];
+        const uint4* wb = wbuf[it & 1];
+        const float* mb = mbuf[it & 1];
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+            if (act[t]) {
+                const f32x16_t s = C::tileT(a[t], zb, lane);
+                bf16x8_t ah[2], al[2];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const float pq = fast_exp2(s[q]);
+                    r[t] += pq;
+                    rm[t] = fmaf(pq, mb[acc_row(q, lane)], rm[t]);
+                    const __bf16 h = (__bf16)pq;
+                    ah[q >> 3][q & 7] = h;
+                    al[q >> 3][q & 7] = (__bf16)(pq - (float)h);
+                }
+#pragma unroll
+                for (int es = 0; es < ES; ++es)
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb) {
+                        const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, wb[((es * 2 + kb) * 2 + 0) * 64 + lane]);
+                        const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, wb[((es * 2 + kb) * 2 + 1) * 64 + lane]);
+                        tacc[t][es] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kb], bh, tacc[t][es], 0, 0, 0);
+                        tacc[t][es] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kb], bl, tacc[t][es], 0, 0, 0);
+                        tacc[t][es] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kb], bh, tacc[t][es], 0, 0, 0);
+                    }
+            }
+        }
+        if (cc == nch - 1) {
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                if (act[t]) {
+                    const float rt = r[t] + shfl_xor_f(r[t], 32);
+                    const float rmt = rm[t] + shfl_xor_f(rm[t], 32);
+                    const int row = (rchunk0 + t) * 32 + (lane & 31);
+                    if (lane < 32) {
+                        p.rp[(size_t)cb * p.n_pad + row] = rt;
+                        p.rmp[(size_t)cb * p.n_pad + row] = rmt;
+                    }
+                    // lane = payload column, q = row acc_row(q, lane)
+#pragma unroll
+                    for (int es = 0; es < ES; ++es)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const size_t rr = (size_t)cb * p.n_pad + (size_t)(rchunk0 + t) * 32 + acc_row(q, lane);
+                            p.Tp[rr * p.tw + es * 32 + (lane & 31)] = tacc[t][es][q];
+                        }
+                }
+            }
+        }
+        if (has_next) {
+            st.store(zbuf[(it + 1) & 1], tid);
+            sw.store(wbuf[(it + 1) & 1], tid);
+            if (tid < 32) mbuf[(it + 1) & 1][tid] = mnext;
         }
         __syncthreads();
     }
@@ -247,12 +414,44 @@ int cov_tw(int path, int dw) {
     return es * 32;
 }
 
+bool cov_bf16_form(int path, int prec, int d, int dw) {
+    return path == 0 && prec == PREC_BF16 && pack_units(prec, d) <= 9 && cov_tw(0, dw) / 32 <= 4;
+}
+
+// row tiles per wave of the covariance kernels (register budget)
+static int cov_rw(int path, int prec, int d, int dw) {
+    const int units = pack_units(prec, d), es = cov_tw(path, dw) / 32;
+    if (cov_bf16_form(path, prec, d, dw)) return (units <= 5 && es <= 2) ? 2 : 1;
+    return (units <= 9 && es <= 4) ? 2 : 1;
+}
+
 int cov_rows_per_group(int path, int prec, int d, int dw) {
     if (path == 1) return COV_VALU_ROWS;
-    const int units = pack_units(prec, d);
-    const int es = (dw + 31) / 32;
-    const int rw = (units <= 9 && es <= 4) ? 2 : 1;
-    return WAVES * rw * 32;
+    return WAVES * cov_rw(path, prec, d, dw) * 32;
+}
+
+template <int KS, int RW, int ES>
+static hipError_t launch_bf16_cov(const CovArgs& a, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((k_cov_bf16<KS, RW, ES>), dim3(grid), dim3(THREADS), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int KS>
+static hipError_t launch_bf16_cov_es(const CovArgs& a, int es, int rw, int grid, hipStream_t stream) {
+    if constexpr (KS <= 5) {
+        if (rw == 2) {
+            if (es == 1) return launch_bf16_cov<KS, 2, 1>(a, grid, stream);
+            if (es == 2) return launch_bf16_cov<KS, 2, 2>(a, grid, stream);
+            return hipErrorInvalidValue;
+        }
+    }
+    switch (es) {
+        case 1: return launch_bf16_cov<KS, 1, 1>(a, grid, stream);
+        case 2: return launch_bf16_cov<KS, 1, 2>(a, grid, stream);
+        case 3: return launch_bf16_cov<KS, 1, 3>(a, grid, stream);
+        case 4: return launch_bf16_cov<KS, 1, 4>(a, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <class C, int RW>
@@ -269,11 +468,11 @@ static hipError_t launch_cov_mfma_es(const CovArgs& a, int es, int grid, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, const float* X, const float* xn,
-                      const float* U, const float* Ul, const float* Zs, const float* ms, const float* V,
-                      const float* Vl, float kappa, const float* W, const float* mw, int dw, int64_t n_pad,
-                      int64_t m_pad, int rg, int bc_chunks, int n_mt_r, int n_mt_c, const CovOut& out,
-                      hipStream_t stream) {
+hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, const void* PW, const float* X,
+                      const float* xn, const float* U, const float* Ul, const float* Zs, const float* ms,
+                      const float* V, const float* Vl, float kappa, const float* W, const float* mw, int dw,
+                      int64_t n_pad, int64_t m_pad, int rg, int bc_chunks, int n_mt_r, int n_mt_c,
+                      const CovOut& out, hipStream_t stream) {
     const int grid = n_mt_r * n_mt_c;
     if (path == 1) {
         if (dw > MAX_VALU_W) return hipErrorInvalidValue;
@@ -318,6 +517,7 @@ hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, c
     CovArgs a;
     a.A = (const uint4*)A;
     a.B = (const uint4*)B;
+    a.PW = (const uint4*)PW;
     a.W = W;
     a.mw = mw;
     a.dw = dw;
@@ -335,6 +535,19 @@ hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, c
     a.m_pad = (int)m_pad;
     const int es = out.tw / 32;
     const int units = pack_units(prec, d);
+    if (cov_bf16_form(path, prec, d, dw)) {
+        if (!PW) return hipErrorInvalidValue;
+        const int rw = cov_rw(path, prec, d, dw);
+        switch (units) {
+            case 2: return launch_bf16_cov_es<2>(a, es, rw, grid, stream);
+            case 3: return launch_bf16_cov_es<3>(a, es, rw, grid, stream);
+            case 4: return launch_bf16_cov_es<4>(a, es, rw, grid, stream);
+            case 5: return launch_bf16_cov_es<5>(a, es, rw, grid, stream);
+            case 7: return launch_bf16_cov_es<7>(a, es, rw, grid, stream);
+            case 9: return launch_bf16_cov_es<9>(a, es, rw, grid, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (prec == PREC_F32) {
         switch (units) {
             case 3: return launch_cov_mfma_es<CoreF32<3>, 2>(a, es, grid, stream);

@@ -309,6 +309,7 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
     c_.prof.end(st_);
     GW_HIP(gwk::launch_norms_logw(X_, n, n_pad_, D_, a, asum, xn_, la2_, st_));
     GW_HIP(gwk::launch_norms_logw(Y_, m, m_pad_, E_, b, bsum, ym_, lb2_, st_));
+    if (pwY_) GW_HIP(gwk::launch_pack_payload(Y_, m, m_pad_, E_, pwY_, st_));
 
     // initial state
     if (gamma0) {
@@ -383,6 +384,8 @@ Status Solve::buffers(bool dry) {
         packB_[0] = getf("pB0", bb / 4);
         packB_[1] = getf("pB1", bb / 4);
     }
+    pwY_ = gwk::cov_bf16_form(geo_.path, prec_, D_, E_) ? (void*)getf("pwY", gwk::payload_pack_bytes(m_pad_, E_) / 4)
+                                                         : nullptr;
     Zs_ = getf("Zs", (size_t)m_pad_ * D_);
     beta_ = getd("beta", m_pad_);
     ms_ = getf("ms", m_pad_);
@@ -508,7 +511,7 @@ Status Solve::covariance(int rows_side, float* T_out, float* r_out, float* rm_ou
     gwk::CovOut out{Tp_, crp_, crmp_, 0};
     if (rows_side == 0) {
         out.tw = cov_tw_;
-        GW_HIP(gwk::launch_cov(geo_.path, prec_, D_, packA_[pa_], packB_[pb_], X_, xn_, U_[pa_], Ul_[pa_], Zs_,
+        GW_HIP(gwk::launch_cov(geo_.path, prec_, D_, packA_[pa_], packB_[pb_], pwY_, X_, xn_, U_[pa_], Ul_[pa_], Zs_,
                                geo_.path == 1 ? ym_ : ms_, V_[pb_], Vl_[pb_], (float)kappa_, Y_, ym_, E_, n_pad_,
                                m_pad_, cov_rg_, cov_bc_, cov_mtr_, cov_mtc_, out, st_));
         GW_HIP(gwk::launch_cov_reduce(out, cov_mtc_, n_, n_pad_, X_, D_, xn_, E_, T_out, r_out, rm_out, part_, st_));
@@ -519,7 +522,13 @@ Status Solve::covariance(int rows_side, float* T_out, float* r_out, float* rm_ou
     // n <-> m, U <-> V), so the same kernels run with the packs swapped and
     // X as the payload; gives T'_j = sum_i pi_ij X_i and sum_i pi_ij |X_i|^2
     out.tw = cov2_tw_;
-    GW_HIP(gwk::launch_cov(geo_.path, prec_, D_, packB_[pb_], packA_[pa_], Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_,
+    if (gwk::cov_bf16_form(geo_.path, prec_, D_, D_) && !pwX_) {
+        Status st;
+        pwX_ = c_.ws.get(tag_ + "pwX", gwk::payload_pack_bytes(n_pad_, D_), &st);
+        if (!st.good()) return st;
+        GW_HIP(gwk::launch_pack_payload(X_, n_, n_pad_, D_, pwX_, st_));
+    }
+    GW_HIP(gwk::launch_cov(geo_.path, prec_, D_, packB_[pb_], packA_[pa_], pwX_, Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_,
                            U_[pa_], Ul_[pa_], (float)kappa_, X_, xn_, D_, m_pad_, n_pad_, cov2_rg_, cov2_bc_,
                            cov2_mtr_, cov2_mtc_, out, st_));
     GW_HIP(gwk::launch_cov_reduce(out, cov2_mtc_, m_, m_pad_, Y_, E_, ym_, D_, T_out, r_out, rm_out, part_, st_));

@@ -211,6 +211,9 @@ class Solve {
     float *X_ = nullptr, *Y_ = nullptr, *xn_ = nullptr, *ym_ = nullptr, *la2_ = nullptr, *lb2_ = nullptr;
     void* packA_[2] = {nullptr, nullptr};
     void* packB_[2] = {nullptr, nullptr};
+    // BF16 form: covariance payload packs (Y for source rows, X for target rows)
+    void* pwY_ = nullptr;
+    void* pwX_ = nullptr;
     // potentials in log2 units as FP32 (hi, lo) pairs, two parities
     float *U_[2] = {nullptr, nullptr}, *V_[2] = {nullptr, nullptr};
     float *Ul_[2] = {nullptr, nullptr}, *Vl_[2] = {nullptr, nullptr};

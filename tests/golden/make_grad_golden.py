@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import gw_oracle as O  # noqa: E402
-from workloads import grad_points, landmark_indices  # noqa: E402
+from workloads import c5_subsample, grad_points, landmark_indices  # noqa: E402
 
 CASES = {
     # name: (seed, n, m, d, penalty, lifted_dim, n_landmarks, eps, outer tolerance)
@@ -32,7 +32,12 @@ CASES = {
     "power16": (61, 230, 190, 3, "power", 16, 96, 0.3, 1e-11),
     # 40-dimensional features scaled to norms of order 1 (see SCALE)
     "features40": (62, 200, 170, 40, "features", 0, 0, 0.3, 1e-10),
+    # a subsample of the differentiation workload (d = 16, Dirichlet weights,
+    # |x - x'| lifted to D = 64); eps 0.05 so that the FP64 reference converges
+    "c5sub": (65, 300, 250, 16, "power", 64, 128, 0.05, 1e-10),
 }
+# cases whose inputs come from workloads.c5_subsample instead of grad_points
+C5 = {"c5sub"}
 # input scale per case: N(0, I_d) points have |x|^2 ~ d, and a cost range of
 # hundreds against eps / 8 makes every converged Sinkhorn solve crawl
 SCALE = {"features40": 40 ** -0.5}
@@ -40,7 +45,10 @@ SCALE = {"features40": 40 ** -0.5}
 
 def features(case):
     seed, n, m, d, pen, D, nl, eps, _ = CASES[case]
-    x, a, y, b = grad_points(seed, n, m, d, noise=0.02 if pen == "power" else 0.05, scale=SCALE.get(case, 1.0))
+    if case in C5:
+        x, a, y, b = c5_subsample(n, m, seed)
+    else:
+        x, a, y, b = grad_points(seed, n, m, d, noise=0.02 if pen == "power" else 0.05, scale=SCALE.get(case, 1.0))
     if pen == "power":
         ix, iy = landmark_indices(n, nl, seed + 1), landmark_indices(m, nl, seed + 2)
         lmx, lmy = O.fit_landmarks(x[ix], 1.0, D), O.fit_landmarks(y[iy], 1.0, D)
@@ -64,6 +72,7 @@ def run(case):
     out = {
         "case": case, "seed": seed, "n": n, "m": m, "d": d, "penalty": pen, "lifted_dim": D,
         "n_landmarks": nl, "eps": eps, "outer_tol": tol, "scale": SCALE.get(case, 1.0),
+        "inputs": "c5_subsample" if case in C5 else "grad_points",
         "landmarks_x": None if lm is None else lm[0].tolist(),
         "landmarks_y": None if lm is None else lm[1].tolist(),
         "gamma": gam.tolist(), "f": f.tolist(), "g": g.tolist(), "loss_lift": O.lifted_loss(X, Y, a, b, pi),

@@ -25,7 +25,7 @@ import pytest
 import torch
 
 from oracle import gw_oracle as O
-from workloads import grad_points
+from workloads import c5_subsample, grad_points
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -42,8 +42,12 @@ def _rel(u, v):
 def _case(name):
     with open(os.path.join(GOLD, f"grad_{name}.json")) as fh:
         gold = json.load(fh)
-    noise = 0.02 if gold["penalty"] == "power" else 0.05
-    x, a, y, b = grad_points(gold["seed"], gold["n"], gold["m"], gold["d"], noise=noise, scale=gold.get("scale", 1.0))
+    if gold.get("inputs") == "c5_subsample":
+        x, a, y, b = c5_subsample(gold["n"], gold["m"], gold["seed"])
+    else:
+        noise = 0.02 if gold["penalty"] == "power" else 0.05
+        x, a, y, b = grad_points(gold["seed"], gold["n"], gold["m"], gold["d"], noise=noise,
+                                 scale=gold.get("scale", 1.0))
     return gold, x, a, y, b
 
 
@@ -76,6 +80,8 @@ def _context(gw, gold, x, a, y, b):
     ("features40", "bf16x3", 1e-4),
     ("features40", "bf16", 3e-2),
     ("power16", "fp32", 1e-4),
+    ("c5sub", "fp32", 1e-4),
+    ("c5sub", "bf16", 3e-2),
 ])
 def test_gradients_match_oracle(gw, case, prec, tol):
     gold, x, a, y, b = _case(case)

@@ -1,0 +1,60 @@
+"""Full-size parity: 200,000 x 200,000 with D = E = 64, in the pass geometry
+the bench times (stabilised and safe passes, combine and final check at that
+shape), on outputs the FP64 oracle computes one by one.
+
+From a seeded state (features, Gamma_0, f = g = 0) the GPU runs one
+symmetric Sinkhorn iteration (Algorithm 3).  tests/golden/make_scale_golden.py
+(oracle only) stores the same update for 4096 sampled rows and 4096 sampled
+columns, each over all 200,000 counterparts, and the bounds derived from the
+arithmetic:
+
+* FP32: each exponent is assembled from terms of magnitude at most S (log2
+  units); a few roundings give |ds| <= 16 ulp(S), so the row's potential
+  moves by at most (eps'/2) ln 2 * 16 * 2^-24 * S;
+* BF16 feature products: rounding X and Z to BF16 changes X_i . Z_j by at
+  most 2^-8 sum_k |X_ik| |Z_jk|, and the update of f_i moves by at most the
+  largest such change over j (log-sum-exp is 1-Lipschitz in the max norm),
+  which is below 2^-8 sum_k |X_ik| max_j |Z_jk|; plus the FP32 term.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import scale_features, seeded_gamma
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(v):
+    return torch.tensor(np.asarray(v, dtype=np.float32), device="cuda")
+
+
+@pytest.mark.parametrize("eps,prec,mode", [(1.0, "bf16", "stabilised"), (1.0, "fp32", "stabilised"),
+                                           (0.1, "bf16", "auto")])
+def test_one_iteration_at_full_size(gw, eps, prec, mode):
+    with open(os.path.join(GOLD, f"scale200k_eps{eps:g}.json")) as fh:
+        gold = json.load(fh)
+    n, d, seeds = gold["n"], gold["d"], gold["seeds"]
+    x = scale_features(seeds["x"], n, d)
+    y = scale_features(seeds["y"], gold["m"], d)
+    gam = seeded_gamma(seeds["gamma"], d, d)
+    a = np.full(n, 1.0 / n)
+    b = np.full(gold["m"], 1.0 / gold["m"])
+    ctx = gw.Context()
+    ctx.set_penalty(2, "features")
+    res = ctx.solve(dev(x), dev(a), dev(y), dev(b), eps, eps, 1, 1, precision=prec, mode=mode, gamma0=dev(gam))
+    rows, cols = np.array(gold["rows"]), np.array(gold["cols"])
+    f = res["f"].cpu().numpy().astype(np.float64)[rows]
+    g = res["g"].cpu().numpy().astype(np.float64)[cols]
+    tol_r = np.array(gold["tol_fp32_rows"]) + (np.array(gold["tol_bf16_rows"]) if prec == "bf16" else 0.0)
+    tol_c = np.array(gold["tol_fp32_cols"]) + (np.array(gold["tol_bf16_cols"]) if prec == "bf16" else 0.0)
+    er, ec = np.abs(f - np.array(gold["f1"])), np.abs(g - np.array(gold["g1"]))
+    print(f"eps {eps} {prec} {mode}: rows max err {er.max():.3e} (bounds {tol_r.min():.2e}..{tol_r.max():.2e}, "
+          f"worst ratio {(er / tol_r).max():.3f}), cols max err {ec.max():.3e} (worst ratio {(ec / tol_c).max():.3f}), "
+          f"mean err {er.mean():.2e} {ec.mean():.2e}, safe iters {res['safe_iters']}")
+    assert np.all(er <= tol_r)
+    assert np.all(ec <= tol_c)

@@ -18,4 +18,7 @@ from .synth import (  # noqa: F401
     rotated_copy,
     landmark_indices,
     grad_points,
+    scale_features,
+    c5_subsample,
+    seeded_gamma,
 )

@@ -174,6 +174,34 @@ def grad_points(seed: int, n: int, m: int, d: int, noise: float = 0.05, scale: f
     return f32(x), a / a.sum(), f32(y), b / b.sum()
 
 
+def c5_subsample(n_src: int, n_tgt: int, seed: int):
+    """A seeded subsample of the differentiation workload (50,000 x 30,000,
+    d = 16, Dirichlet weights), rounded to float32 with the weights
+    renormalised in float64.  Returns (x, a, y, b)."""
+    sub = subsample(config5_grad(), n_src, n_tgt, seed)
+    f32 = lambda v: np.asarray(v, dtype=np.float32).astype(np.float64)  # noqa: E731
+    a, b = f32(sub.a), f32(sub.b)
+    return f32(sub.x), a / a.sum(), f32(sub.y), b / b.sum()
+
+
+def scale_features(seed: int, n: int, d: int, decay: float = 1.5) -> np.ndarray:
+    """Feature clouds shaped like landmark kernel-PCA features: independent
+    Gaussian coordinates with variances proportional to k^-decay
+    (k = 1..d), total variance 1.  Float32-representable float64."""
+    rng = np.random.default_rng(seed)
+    var = np.arange(1, d + 1, dtype=np.float64) ** -decay
+    var /= var.sum()
+    x = rng.standard_normal((n, d)) * np.sqrt(var)[None, :]
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def seeded_gamma(seed: int, d: int, e: int, scale: float = 0.5) -> np.ndarray:
+    """A D x E starting map: scale times the first rows/columns of a Haar
+    orthogonal matrix.  Float32-representable float64."""
+    q = haar_rotation(np.random.default_rng(seed), max(d, e))[:d, :e]
+    return np.asarray(scale * q, dtype=np.float32).astype(np.float64)
+
+
 def landmark_indices(n: int, n_landmarks: int, seed: int) -> np.ndarray:
     """Landmark subset for kernel PCA: the first n_l entries of a seeded
     permutation, sorted.  A random draw of the method, so both the oracle and
