@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three plain 256 MiB device copies first, as the scale for HBM byte counters")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving workload and print its measurements (for profiling it)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-landmarks", type=int, default=512)
@@ -167,6 +169,9 @@ def main():
     from workloads import config3_scale, landmark_indices
 
     dev = torch.device("cuda:0")
+    if args.serve_only:
+        print(json.dumps({"serving": serve_bench(args, gwm, torch, dev)}), flush=True)
+        return
     prob = config3_scale(n=args.n, lifted_dim=args.dim)
     n, m = prob.n, prob.m
     t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
