@@ -35,6 +35,45 @@ EXP_SLOTS = 2.0      # v_exp_f32 issues at half the FP32 rate on gfx950 (measure
 ADD_SLOTS = 2.0
 
 
+PASS_SOURCES = ["k_sinkhorn.hip", "gw_cores.h", "gw_device.h", "gw_layout.h", "gw_kernels.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_stab_gmm200k_bf16_hbm_traffic.txt")
+
+
+def pass_source_hash() -> str:
+    """Hash of the stabilised pass's sources and compile flags: counter
+    results apply only to the kernel they were taken on."""
+    import hashlib
+
+    from paper_2602_06658_amd import build as B
+
+    h = hashlib.sha1()
+    for name in PASS_SOURCES:
+        with open(os.path.join(B.CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(B.COMMON).encode())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the stabilised pass from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None if the summary is missing or was taken on other sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as fh:
+        for ln in fh:
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_hash") != pass_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def alu_peak_entries_per_s() -> float:
     lane_ops = CUS * SIMDS_PER_CU * LANES_PER_CLK * CLOCK_HZ
     return lane_ops / (EXP_SLOTS + ADD_SLOTS)
@@ -252,7 +291,7 @@ def main():
                                f"{args.n_outer}x{args.n_inner} symmetric Sinkhorn",
                    "global_batch": 1, "seq_len": n, "parallelism": "none"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gentry/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": recorded_traffic(),
                      "kernel": "k_pass_stab (stabilised Sinkhorn pass)",
                      "avg_launch_ms": avg_ms, "launches": st["launches"]},
         "solve": {k: res[k] for k in ("loss_lift", "egw_objective", "kl", "marginal_err", "gamma_step",

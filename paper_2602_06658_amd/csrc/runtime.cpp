@@ -80,6 +80,25 @@ void Workspace::release_prefix(const std::string& prefix) {
 // Profiler
 // ---------------------------------------------------------------------------
 
+void* Ctx::host_stage(size_t bytes, Status* st) {
+    if (bytes > stage_bytes_) {
+        if (stage_) (void)hipHostFree(stage_);
+        stage_ = nullptr;
+        stage_bytes_ = 0;
+        if (hipHostMalloc(&stage_, bytes, hipHostMallocDefault) != hipSuccess) {
+            stage_ = nullptr;
+            *st = fail(GW_ENOMEM, "pinned host staging");
+            return nullptr;
+        }
+        stage_bytes_ = bytes;
+    }
+    return stage_;
+}
+
+Ctx::~Ctx() {
+    if (stage_) (void)hipHostFree(stage_);
+}
+
 hipEvent_t Profiler::take() {
     if (!pool_.empty()) {
         hipEvent_t e = pool_.back();
@@ -585,6 +604,12 @@ Status Solve::end_outer() {
 }
 
 Status Solve::finish(gw_result* out) {
+    GW_TRY(finish_enqueue(out));
+    GW_HIP(hipStreamSynchronize(st_));
+    return finish_collect(out);
+}
+
+Status Solve::finish_enqueue(gw_result* out) {
     Status st;
     auto& ws = c_.ws;
     // FP64 check of the final coupling (f_T, g_T, Gamma_{T-1})
@@ -622,14 +647,27 @@ Status Solve::finish(gw_result* out) {
     if (out->gamma)
         GW_HIP(hipMemcpyAsync(out->gamma, gam_[gcur_], (size_t)D_ * E_ * sizeof(float), hipMemcpyDeviceToDevice,
                               st_));
-    std::vector<double> hs(16), mx(2 + D_ * D_ + D_), my(2 + E_ * E_ + E_);
-    int hctl[CTL_WORDS];
-    GW_HIP(hipMemcpyAsync(hs.data(), scal_, 16 * sizeof(double), hipMemcpyDeviceToHost, st_));
-    GW_HIP(hipMemcpyAsync(mx.data(), momx_, mx.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
-    GW_HIP(hipMemcpyAsync(my.data(), momy_, my.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
-    GW_HIP(hipMemcpyAsync(hctl, ctl_, sizeof(hctl), hipMemcpyDeviceToHost, st_));
-    GW_HIP(hipStreamSynchronize(st_));
-    auto cpart = [](const std::vector<double>& mo, int d) {
+    // scalars, moments and control words to pinned host memory
+    const size_t nmx = 2 + (size_t)D_ * D_ + D_, nmy = 2 + (size_t)E_ * E_ + E_;
+    const size_t bytes = (16 + nmx + nmy) * sizeof(double) + CTL_WORDS * sizeof(int);
+    double* h = (double*)c_.host_stage(bytes, &st);
+    if (!st.good()) return st;
+    GW_HIP(hipMemcpyAsync(h, scal_, 16 * sizeof(double), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipMemcpyAsync(h + 16, momx_, nmx * sizeof(double), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipMemcpyAsync(h + 16 + nmx, momy_, nmy * sizeof(double), hipMemcpyDeviceToHost, st_));
+    GW_HIP(hipMemcpyAsync(h + 16 + nmx + nmy, ctl_, CTL_WORDS * sizeof(int), hipMemcpyDeviceToHost, st_));
+    return Status::ok();
+}
+
+Status Solve::finish_collect(gw_result* out) {
+    const size_t nmx = 2 + (size_t)D_ * D_ + D_, nmy = 2 + (size_t)E_ * E_ + E_;
+    Status st;
+    const double* hs = (const double*)c_.host_stage(0, &st);
+    if (!hs) return fail(GW_ESTATE, "finish_collect without finish_enqueue");
+    const double* mx = hs + 16;
+    const double* my = hs + 16 + nmx;
+    const int* hctl = (const int*)(hs + 16 + nmx + nmy);
+    auto cpart = [](const double* mo, int d) {
         double s = mo[0], m4 = mo[1], sig2 = 0.0;
         for (int k = 0; k < d * d; ++k) sig2 += mo[2 + k] * mo[2 + k];
         return 2.0 * m4 + 4.0 * sig2 + 2.0 * s * s;

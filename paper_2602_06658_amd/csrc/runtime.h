@@ -124,6 +124,14 @@ struct Ctx {
     SideCfg side[2];
     void* rocblas = nullptr;  // rocblas_handle, created on first eigensolve
     std::mutex mu;
+    // Pinned host staging for result readback, grown on demand; bytes = 0
+    // returns the current buffer.
+    void* host_stage(size_t bytes, Status* st);
+    ~Ctx();
+
+   private:
+    void* stage_ = nullptr;
+    size_t stage_bytes_ = 0;
 };
 
 int feature_dim(const SideCfg& s, int d);
@@ -149,8 +157,15 @@ class Solve {
     Status outer_step();
     bool done() const { return done_; }
     int outer_done() const { return t_; }
-    // FP64 final check and result readback (blocks on the stream).
+    // FP64 final check and result readback (blocks on the stream) =
+    // finish_enqueue, a wait for the stream, finish_collect.  The split form
+    // lets a caller wait on an event instead (serving loop).
     Status finish(gw_result* out);
+    Status finish_enqueue(gw_result* out);
+    Status finish_collect(gw_result* out);
+    // Move the solve's later work to another stream (after an event on the
+    // old one has been made a dependency of the new one).
+    void set_stream(hipStream_t s) { st_ = s; }
     // Gradients of the final state (after finish).
     Status gradients(float* grad_x, float* grad_a, float* grad_y, float* grad_b);
 

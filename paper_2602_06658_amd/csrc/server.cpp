@@ -1,22 +1,30 @@
 // Serving loop: continuous batching of independent CNT-GW solves (Algorithm 1)
 // on one GPU.
 //
-// A host thread owns every GPU-side step of the requests it has admitted.
-// Requests wait in a FIFO queue and are admitted while a slot is free and
-// their planned device footprint fits the HBM budget; admission happens
-// between Sinkhorn iterations, so a request that arrives while others run
-// joins them at the next round.  Each round advances every active request by
-// one Sinkhorn iteration: symmetric MFMA-path requests go through one
-// batched launch per kernel (pass, safe pass, combine, retry pass, retry
-// combine) over a table of up to 16 requests, whose work-groups share the
-// GPU; other requests launch their own kernels.  A request's prologue and
-// covariance run at its own outer-step boundaries.  Finished requests are
-// checked in FP64 (Appendix A.1's Err), their results recorded, and their
-// device memory released.
+// Two host threads share the work of the requests a server has admitted:
 //
-// Each request has its own context (workspace, penalties, landmarks) and
-// runs the same kernels as gw_solve with the same per-problem arguments, so
-// its result does not depend on what else is in the batch.
+// * the setup thread takes admitted requests in FIFO order and runs their
+//   setup (validation, lifting with its landmark eigensolve, initial state) on
+//   a stream of its own, then records an event and hands the request over;
+// * the round thread issues rounds on the context's stream: every active
+//   request advances by one Sinkhorn iteration.  Symmetric MFMA-path requests
+//   go through one batched launch per kernel (pass, safe pass, combine, retry
+//   pass, retry combine) over a table of up to 16 requests whose work-groups
+//   share the GPU; other requests launch their own kernels.  A request's
+//   prologue and covariance run at its own outer-step boundaries.  A finished
+//   request's FP64 check (Appendix A.1's Err) and result readback are queued
+//   behind its last round and collected when an event says they are done.
+//
+// Neither thread waits for the other's GPU work: a request joins the rounds
+// once the round stream has been made to wait on its setup event, so setups
+// and their host-side synchronisations overlap the rounds of others.
+// Requests are admitted while a slot is free and their planned device
+// footprint fits the HBM budget.  Request contexts (workspace, pinned
+// staging, event) are pooled and reused, so the rounds never wait for a
+// device free.
+//
+// Each request runs the same kernels as gw_solve with the same per-problem
+// arguments, so its result does not depend on what else is in the batch.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -38,7 +46,13 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-enum ReqState { RQ_QUEUED, RQ_ACTIVE, RQ_DONE, RQ_CANCELLED, RQ_FAILED };
+enum ReqState { RQ_QUEUED, RQ_SETUP, RQ_ACTIVE, RQ_DONE, RQ_CANCELLED, RQ_FAILED };
+
+// A pooled request context: workspace, penalties, pinned staging, event.
+struct Slot {
+    std::unique_ptr<gwr::Ctx> ctx;
+    hipEvent_t ev = nullptr;
+};
 
 struct Request {
     uint64_t ticket = 0;
@@ -51,8 +65,8 @@ struct Request {
     gw_result res{};
     size_t footprint = 0;
     bool cancel = false;
-    // GPU-side state, touched by the server thread only
-    std::unique_ptr<gwr::Ctx> ctx;
+    // GPU-side state, owned by one thread at a time (setup, then rounds)
+    Slot* slot = nullptr;
     std::unique_ptr<gwr::Solve> solve;
     int k = 0;
     bool in_outer = false;
@@ -64,17 +78,24 @@ struct gw_server {
     gwr::Ctx* base = nullptr;
     int max_slots = 1;
     size_t budget = 0;
-    std::thread th;
+    hipStream_t setup_stream = nullptr;
+    std::thread th, worker;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_setup, cv_done;
     bool stop = false;
     uint64_t next_ticket = 1;
-    std::deque<uint64_t> queue;
+    std::deque<uint64_t> queue;           // submitted, not admitted
+    std::deque<Request*> to_setup;        // admitted, waiting for the setup thread
+    std::vector<Request*> ready;          // set up, waiting to join the rounds
+    std::vector<std::unique_ptr<Slot>> free_slots;
+    std::vector<std::unique_ptr<Slot>> used_slots;
+    int in_flight = 0;                    // admitted and not yet completed
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     gw_server_stats stats{};
     size_t resident = 0;
-    void* rocblas = nullptr;  // shared by the requests' landmark eigensolves
-    std::vector<Request*> active;  // server thread only
+    void* rocblas = nullptr;              // used by the setup thread only
+    // round thread only
+    std::vector<Request*> active, finishing;
 };
 
 namespace {
@@ -87,26 +108,45 @@ void configure_sides(gwr::Ctx& c, const gw_request& r) {
         sc.lifted_dim = r.lifted_dim;
         sc.n_landmarks = r.n_landmarks;
         sc.seed = r.seed + (uint64_t)s;
+        sc.explicit_idx.clear();
+        sc.lm.fitted = false;
     }
 }
 
-std::unique_ptr<gwr::Ctx> make_ctx(gw_server* s, const gw_request& r) {
-    auto c = std::make_unique<gwr::Ctx>();
-    c->device = s->base->device;
-    c->stream = s->base->stream;
-    configure_sides(*c, r);
-    return c;
+Slot* acquire_slot(gw_server* s) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->free_slots.empty()) {
+        std::unique_ptr<Slot> sl = std::move(s->free_slots.back());
+        s->free_slots.pop_back();
+        Slot* p = sl.get();
+        s->used_slots.push_back(std::move(sl));
+        return p;
+    }
+    auto sl = std::make_unique<Slot>();
+    sl->ctx = std::make_unique<gwr::Ctx>();
+    sl->ctx->device = s->base->device;
+    (void)hipEventCreateWithFlags(&sl->ev, hipEventDisableTiming);
+    Slot* p = sl.get();
+    s->used_slots.push_back(std::move(sl));
+    return p;
 }
 
-// Free a request's device memory (the stream must be idle for it).
-void release(gw_server* s, Request* q) {
-    if (q->ctx) {
-        if (q->ctx->rocblas == s->rocblas) q->ctx->rocblas = nullptr;  // shared handle stays
-        gwr::release_landmarks(*q->ctx);
-        q->ctx->ws.release_all();
-    }
+// Return a slot whose GPU work has completed.  Its landmark data is freed
+// (only read while lifting); the workspace stays for the next request.
+void release_slot(gw_server* s, Request* q) {
     q->solve.reset();
-    q->ctx.reset();
+    Slot* sl = q->slot;
+    q->slot = nullptr;
+    if (!sl) return;
+    if (sl->ctx->rocblas == s->rocblas) sl->ctx->rocblas = nullptr;  // shared handle stays
+    gwr::release_landmarks(*sl->ctx);
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto it = s->used_slots.begin(); it != s->used_slots.end(); ++it)
+        if (it->get() == sl) {
+            s->free_slots.push_back(std::move(*it));
+            s->used_slots.erase(it);
+            break;
+        }
 }
 
 void complete(gw_server* s, Request* q, ReqState st, gw_status code, const std::string& msg) {
@@ -116,14 +156,20 @@ void complete(gw_server* s, Request* q, ReqState st, gw_status code, const std::
     q->msg = msg;
     q->latency = std::chrono::duration<double>(Clock::now() - q->t_submit).count();
     s->resident -= q->footprint;
-    if (st == RQ_DONE) s->stats.completed++;
+    s->in_flight--;
+    if (st == RQ_DONE || st == RQ_FAILED) s->stats.completed++;
     if (st == RQ_CANCELLED) s->stats.cancelled++;
-    if (st == RQ_FAILED) s->stats.completed++;
     s->cv_done.notify_all();
+    s->cv_work.notify_all();
 }
 
+// Setup of one request on the setup stream (validation, lifting, initial
+// state); the host-side waits in it block only the setup thread.
 gwr::Status start(gw_server* s, Request* q) {
-    q->ctx = make_ctx(s, q->r);
+    q->slot = acquire_slot(s);
+    gwr::Ctx& c = *q->slot->ctx;
+    c.stream = s->setup_stream;
+    configure_sides(c, q->r);
     if (q->r.penalty == GW_PEN_POWER) {
         if (!s->rocblas) {
             rocblas_handle h;
@@ -131,19 +177,49 @@ gwr::Status start(gw_server* s, Request* q) {
                 return gwr::fail(GW_EDEVICE, "rocblas_create_handle");
             s->rocblas = h;
         }
-        q->ctx->rocblas = s->rocblas;
+        c.rocblas = s->rocblas;
     }
-    q->solve = std::make_unique<gwr::Solve>(*q->ctx, "q.");
+    q->solve = std::make_unique<gwr::Solve>(c, "q.");
     const gw_request& r = q->r;
-    GW_TRY(gwr::validate_inputs(*q->ctx, r.x, r.n, r.dx, r.a, r.y, r.m, r.dy, r.b, &r.params, "q."));
+    GW_TRY(gwr::validate_inputs(c, r.x, r.n, r.dx, r.a, r.y, r.m, r.dy, r.b, &r.params, "q."));
     GW_TRY(q->solve->setup(r.x, r.n, r.dx, r.a, r.y, r.m, r.dy, r.b, r.params, nullptr, nullptr, nullptr, r.penalty,
-                           r.penalty, q->ctx->stream));
+                           r.penalty, c.stream));
+    GW_HIP(hipEventRecord(q->slot->ev, c.stream));
     q->k = 0;
     q->in_outer = false;
     return gwr::Status::ok();
 }
 
-// One round: every active request advances by one Sinkhorn iteration.
+void setup_main(gw_server* s) {
+    (void)hipSetDevice(s->base->device);
+    for (;;) {
+        Request* q = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_setup.wait(lk, [&] { return s->stop || !s->to_setup.empty(); });
+            if (s->stop) return;
+            q = s->to_setup.front();
+            s->to_setup.pop_front();
+        }
+        if (q->cancel) {
+            complete(s, q, RQ_CANCELLED, GW_ECANCELLED, "cancelled");
+            continue;
+        }
+        gwr::Status st = start(s, q);
+        if (!st.good()) {
+            (void)hipStreamSynchronize(s->setup_stream);
+            release_slot(s, q);
+            complete(s, q, RQ_FAILED, st.code, st.msg);
+            continue;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->ready.push_back(q);
+        s->cv_work.notify_all();
+    }
+}
+
+// One round on the main stream: every active request advances by one
+// Sinkhorn iteration.
 gwr::Status round(gw_server* s, std::vector<Request*>& finished) {
     std::vector<gwk::PassItem> items;
     std::vector<gwk::CombineArgs> mains, retries;
@@ -189,123 +265,140 @@ gwr::Status round(gw_server* s, std::vector<Request*>& finished) {
     return gwr::Status::ok();
 }
 
-void fail_all_active(gw_server* s, const gwr::Status& st) {
+void drop_all_active(gw_server* s, ReqState st, gw_status code, const std::string& msg) {
     (void)hipStreamSynchronize(s->base->stream);
     for (Request* q : s->active) {
-        release(s, q);
-        complete(s, q, RQ_FAILED, st.code, st.msg);
+        release_slot(s, q);
+        complete(s, q, st, code, msg);
     }
     s->active.clear();
 }
 
-void server_main(gw_server* s) {
+void round_main(gw_server* s) {
     (void)hipSetDevice(s->base->device);
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    (void)hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
-    (void)hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
-    int evi = 0;
-    bool ev_used[2] = {false, false};
+    hipStream_t main = s->base->stream;
+    hipEvent_t pace[2] = {nullptr, nullptr};
+    (void)hipEventCreateWithFlags(&pace[0], hipEventDisableTiming);
+    (void)hipEventCreateWithFlags(&pace[1], hipEventDisableTiming);
+    int pi = 0;
+    bool pace_used[2] = {false, false};
+    bool busy = false;
     Clock::time_point busy_from;
     for (;;) {
-        std::vector<Request*> admit, cancelled;
+        std::vector<Request*> joining, cancelled;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            if (s->active.empty()) {
-                if (s->stats.active == 0 && s->queue.empty() && !s->stop) {
-                    s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            if (s->active.empty() && s->finishing.empty() && s->ready.empty() && !s->stop) {
+                if (busy) {
+                    s->stats.busy_seconds += std::chrono::duration<double>(Clock::now() - busy_from).count();
+                    busy = false;
                 }
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(50),
+                                    [&] { return s->stop || !s->ready.empty() || !s->queue.empty(); });
             }
             if (s->stop) break;
-            for (Request* q : s->active)
-                if (q->cancel) cancelled.push_back(q);
-            // FIFO admission by slot and footprint
-            while (!s->queue.empty() && (int)(s->active.size() + admit.size()) < s->max_slots) {
+            // FIFO admission by slot and footprint; setup happens elsewhere
+            while (!s->queue.empty() && s->in_flight < s->max_slots) {
                 Request* q = s->reqs[s->queue.front()].get();
                 if (s->budget && s->resident + q->footprint > s->budget) break;
                 s->queue.pop_front();
-                q->state = RQ_ACTIVE;
+                q->state = RQ_SETUP;
                 s->resident += q->footprint;
-                admit.push_back(q);
+                s->in_flight++;
+                s->to_setup.push_back(q);
+                s->cv_setup.notify_one();
             }
+            joining.swap(s->ready);
+            for (Request* q : joining) q->state = RQ_ACTIVE;
+            for (Request* q : s->active)
+                if (q->cancel) cancelled.push_back(q);
             s->stats.queued = (int32_t)s->queue.size();
+            s->stats.active = (int32_t)(s->active.size() + joining.size());
+        }
+        if (!busy && (!joining.empty() || !s->active.empty())) {
+            busy = true;
+            busy_from = Clock::now();
+        }
+        for (Request* q : joining) {
+            (void)hipStreamWaitEvent(main, q->slot->ev, 0);
+            q->slot->ctx->stream = main;
+            q->solve->set_stream(main);
+            s->active.push_back(q);
         }
         if (!cancelled.empty()) {
-            (void)hipStreamSynchronize(s->base->stream);
+            (void)hipStreamSynchronize(main);
             for (Request* q : cancelled) {
                 s->active.erase(std::find(s->active.begin(), s->active.end(), q));
-                release(s, q);
+                release_slot(s, q);
                 complete(s, q, RQ_CANCELLED, GW_ECANCELLED, "cancelled");
             }
         }
-        const bool was_idle = s->active.empty();
-        for (Request* q : admit) {
-            gwr::Status st = start(s, q);
+        if (!s->active.empty()) {
+            std::vector<Request*> finished;
+            gwr::Status st = round(s, finished);
             if (!st.good()) {
-                (void)hipStreamSynchronize(s->base->stream);
-                release(s, q);
-                complete(s, q, RQ_FAILED, st.code, st.msg);
+                drop_all_active(s, RQ_FAILED, st.code, st.msg);
                 continue;
             }
-            s->active.push_back(q);
+            for (Request* q : finished) {
+                q->res = gw_result{};
+                q->res.f = q->r.f;
+                q->res.g = q->r.g;
+                q->res.gamma = q->r.gamma;
+                s->active.erase(std::find(s->active.begin(), s->active.end(), q));
+                gwr::Status fs = q->solve->finish_enqueue(&q->res);
+                if (fs.good() && hipEventRecord(q->slot->ev, main) == hipSuccess) {
+                    s->finishing.push_back(q);
+                } else {
+                    (void)hipStreamSynchronize(main);
+                    release_slot(s, q);
+                    complete(s, q, RQ_FAILED, fs.good() ? GW_EDEVICE : fs.code, fs.good() ? "event" : fs.msg);
+                }
+            }
+            // keep at most two rounds in flight so that arrivals join promptly
+            (void)hipEventRecord(pace[pi], main);
+            pace_used[pi] = true;
+            pi ^= 1;
+            if (pace_used[pi]) (void)hipEventSynchronize(pace[pi]);
+        } else if (!s->finishing.empty()) {
+            (void)hipEventSynchronize(s->finishing.front()->slot->ev);
         }
-        if (s->active.empty()) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stats.active = 0;
-            continue;
+        // collect finished checks whose events have completed
+        for (size_t i = 0; i < s->finishing.size();) {
+            Request* q = s->finishing[i];
+            if (hipEventQuery(q->slot->ev) != hipSuccess) {
+                ++i;
+                continue;
+            }
+            gwr::Status cs = q->solve->finish_collect(&q->res);
+            s->finishing.erase(s->finishing.begin() + i);
+            release_slot(s, q);
+            if (cs.good()) complete(s, q, RQ_DONE, GW_OK, "");
+            else complete(s, q, RQ_FAILED, cs.code, cs.msg);
         }
-        if (was_idle) busy_from = Clock::now();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stats.active = (int32_t)s->active.size();
-        }
-        std::vector<Request*> finished;
-        gwr::Status st = round(s, finished);
-        if (!st.good()) {
-            fail_all_active(s, st);
-            continue;
-        }
-        for (Request* q : finished) {
-            q->res = gw_result{};
-            q->res.f = q->r.f;
-            q->res.g = q->r.g;
-            q->res.gamma = q->r.gamma;
-            gwr::Status fs = q->solve->finish(&q->res);  // FP64 check; waits for the stream
-            s->active.erase(std::find(s->active.begin(), s->active.end(), q));
-            release(s, q);
-            if (fs.good()) complete(s, q, RQ_DONE, GW_OK, "");
-            else complete(s, q, RQ_FAILED, fs.code, fs.msg);
-        }
-        if (s->active.empty()) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stats.busy_seconds += std::chrono::duration<double>(Clock::now() - busy_from).count();
-            s->stats.active = 0;
-        }
-        // keep at most two rounds in flight so admissions stay prompt
-        (void)hipEventRecord(ev[evi], s->base->stream);
-        ev_used[evi] = true;
-        evi ^= 1;
-        if (ev_used[evi]) (void)hipEventSynchronize(ev[evi]);
     }
-    // shutdown: cancel whatever is left
-    (void)hipStreamSynchronize(s->base->stream);
-    for (Request* q : s->active) {
-        release(s, q);
+    // shutdown: everything still resident is cancelled
+    (void)hipStreamSynchronize(main);
+    for (Request* q : s->finishing) {
+        release_slot(s, q);
         complete(s, q, RQ_CANCELLED, GW_ECANCELLED, "server stopped");
     }
-    s->active.clear();
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        for (uint64_t t : s->queue) {
-            Request* q = s->reqs[t].get();
-            q->state = RQ_CANCELLED;
-            q->status = GW_ECANCELLED;
-            s->stats.cancelled++;
-        }
-        s->queue.clear();
-        s->cv_done.notify_all();
-    }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    s->finishing.clear();
+    drop_all_active(s, RQ_CANCELLED, GW_ECANCELLED, "server stopped");
+    (void)hipEventDestroy(pace[0]);
+    (void)hipEventDestroy(pace[1]);
+}
+
+void cancel_unstarted(gw_server* s, Request* q) {
+    q->state = RQ_CANCELLED;
+    q->status = GW_ECANCELLED;
+    s->stats.cancelled++;
+}
+
+void destroy_slot(gw_server* s, Slot& sl) {
+    if (sl.ctx->rocblas == s->rocblas) sl.ctx->rocblas = nullptr;
+    gwr::release_landmarks(*sl.ctx);
+    (void)hipEventDestroy(sl.ev);
 }
 
 }  // namespace
@@ -315,12 +408,18 @@ extern "C" {
 gw_status gw_server_create(gw_ctx* ctx, int max_slots, size_t hbm_budget_bytes, gw_server** out) {
     if (!ctx || !out || max_slots < 1 || max_slots > 64) return GW_EINVAL;
     *out = nullptr;
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return GW_EDEVICE;
     gw_server* s = new (std::nothrow) gw_server();
     if (!s) return GW_ENOMEM;
     s->base = &ctx->c;
     s->max_slots = max_slots;
     s->budget = hbm_budget_bytes;
-    s->th = std::thread(server_main, s);
+    if (hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return GW_EDEVICE;
+    }
+    s->worker = std::thread(setup_main, s);
+    s->th = std::thread(round_main, s);
     *out = s;
     return GW_OK;
 }
@@ -350,12 +449,12 @@ gw_status gw_server_submit(gw_server* s, const gw_request* req, uint64_t* ticket
     s->queue.push_back(q->ticket);
     s->reqs.emplace(q->ticket, std::move(q));
     s->stats.queued = (int32_t)s->queue.size();
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
     return GW_OK;
 }
 
 static gw_status report(Request* q, gw_result* out, double* latency_s) {
-    if (q->state == RQ_QUEUED || q->state == RQ_ACTIVE) return GW_EBUSY;
+    if (q->state == RQ_QUEUED || q->state == RQ_SETUP || q->state == RQ_ACTIVE) return GW_EBUSY;
     if (latency_s) *latency_s = q->latency;
     if (q->state == RQ_CANCELLED) return GW_ECANCELLED;
     if (q->state == RQ_FAILED) return q->status;
@@ -377,7 +476,7 @@ gw_status gw_server_wait(gw_server* s, uint64_t ticket, gw_result* out, double* 
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return GW_EINVAL;
     Request* q = it->second.get();
-    s->cv_done.wait(lk, [&] { return q->state != RQ_QUEUED && q->state != RQ_ACTIVE; });
+    s->cv_done.wait(lk, [&] { return q->state != RQ_QUEUED && q->state != RQ_SETUP && q->state != RQ_ACTIVE; });
     return report(q, out, latency_s);
 }
 
@@ -389,14 +488,12 @@ gw_status gw_server_cancel(gw_server* s, uint64_t ticket) {
     Request* q = it->second.get();
     if (q->state == RQ_QUEUED) {
         s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
-        q->state = RQ_CANCELLED;
-        q->status = GW_ECANCELLED;
+        cancel_unstarted(s, q);
         q->latency = std::chrono::duration<double>(Clock::now() - q->t_submit).count();
-        s->stats.cancelled++;
         s->stats.queued = (int32_t)s->queue.size();
         s->cv_done.notify_all();
-    } else if (q->state == RQ_ACTIVE) {
-        q->cancel = true;
+    } else if (q->state == RQ_SETUP || q->state == RQ_ACTIVE) {
+        q->cancel = true;  // taken by the setup thread or the next round
     }
     return GW_OK;
 }
@@ -414,9 +511,31 @@ void gw_server_destroy(gw_server* s) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
         s->cv_work.notify_all();
+        s->cv_setup.notify_all();
     }
+    if (s->worker.joinable()) s->worker.join();
     if (s->th.joinable()) s->th.join();
+    (void)hipStreamSynchronize(s->setup_stream);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Request* q : s->to_setup) cancel_unstarted(s, q);
+        s->to_setup.clear();
+        for (uint64_t t : s->queue) cancel_unstarted(s, s->reqs[t].get());
+        s->queue.clear();
+    }
+    for (Request* q : s->ready) {
+        release_slot(s, q);
+        std::lock_guard<std::mutex> lk(s->mu);
+        cancel_unstarted(s, q);
+    }
+    s->ready.clear();
+    s->cv_done.notify_all();
+    for (auto& sl : s->free_slots) destroy_slot(s, *sl);
+    for (auto& sl : s->used_slots) destroy_slot(s, *sl);
+    s->free_slots.clear();
+    s->used_slots.clear();
     if (s->rocblas) rocblas_destroy_handle((rocblas_handle)s->rocblas);
+    (void)hipStreamDestroy(s->setup_stream);
     delete s;
 }
 

@@ -76,5 +76,5 @@ def run(eps):
 
 
 if __name__ == "__main__":
-    for e in (sys.argv[1:] or ["1.0", "0.1"]):
+    for e in (sys.argv[1:] or ["4.0", "1.0", "0.1"]):
         run(float(e))
