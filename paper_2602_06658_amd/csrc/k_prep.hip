@@ -355,37 +355,70 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream) {
 // part layout per block: [s, m4, Sigma (d*d), m3 (d)].
 // ---------------------------------------------------------------------------
 
-__global__ void k_moments_part(const float* X, int64_t n, int d, const float* w, double* part, int rows_per_blk) {
+// Rows are staged 32 at a time in LDS with their FP64 norms and weights;
+// block (x, y) covers rows of block x and outputs [2048 y, 2048 (y + 1)),
+// eight per thread, accumulated over the staged rows in order.
+constexpr int MOM_CHUNK = 32, MOM_PER_THREAD = 8, MOM_OUT_BLK = 256 * MOM_PER_THREAD;
+
+__global__ void __launch_bounds__(256) k_moments_part(const float* X, int64_t n, int d, const float* w, double* part,
+                                                      int rows_per_blk) {
+    extern __shared__ float xs[];  // MOM_CHUNK x d
+    __shared__ double nr[MOM_CHUNK], wr[MOM_CHUNK];
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(n, r0 + rows_per_blk);
     const int width = 2 + d * d + d;
-    double* out = part + (size_t)blockIdx.x * width;
-    for (int t = threadIdx.x; t < width; t += blockDim.x) {
-        double acc = 0.0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const float* xr = X + r * d;
-            double nr = 0.0;
-            for (int c = 0; c < d; ++c) nr += (double)xr[c] * (double)xr[c];
-            const double wr = (double)w[r];
-            if (t == 0) acc += wr * nr;
-            else if (t == 1) acc += wr * nr * nr;
-            else if (t < 2 + d * d) {
-                const int u = t - 2;
-                acc += wr * (double)xr[u / d] * (double)xr[u % d];
-            } else {
-                acc += wr * nr * (double)xr[t - 2 - d * d];
+    const int t0 = blockIdx.y * MOM_OUT_BLK + threadIdx.x;
+    double acc[MOM_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < MOM_PER_THREAD; ++k) acc[k] = 0.0;
+    for (int64_t c0 = r0; c0 < r1; c0 += MOM_CHUNK) {
+        const int nc = (int)min((int64_t)MOM_CHUNK, r1 - c0);
+        __syncthreads();
+        for (int u = threadIdx.x; u < nc * d; u += blockDim.x) xs[u] = X[c0 * d + u];
+        __syncthreads();
+        if (threadIdx.x < nc) {
+            double q = 0.0;
+            for (int c = 0; c < d; ++c) {
+                const double v = (double)xs[threadIdx.x * d + c];
+                q += v * v;
             }
+            nr[threadIdx.x] = q;
+            wr[threadIdx.x] = (double)w[c0 + threadIdx.x];
         }
-        out[t] = acc;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MOM_PER_THREAD; ++k) {
+            const int t = t0 + k * 256;
+            if (t >= width) break;
+            double a = acc[k];
+            if (t == 0) {
+                for (int r = 0; r < nc; ++r) a += wr[r] * nr[r];
+            } else if (t == 1) {
+                for (int r = 0; r < nc; ++r) a += wr[r] * nr[r] * nr[r];
+            } else if (t < 2 + d * d) {
+                const int u = (t - 2) / d, v = (t - 2) - u * d;
+                for (int r = 0; r < nc; ++r) a += wr[r] * (double)xs[r * d + u] * (double)xs[r * d + v];
+            } else {
+                const int c = t - 2 - d * d;
+                for (int r = 0; r < nc; ++r) a += wr[r] * nr[r] * (double)xs[r * d + c];
+            }
+            acc[k] = a;
+        }
+    }
+    double* out = part + (size_t)blockIdx.x * width;
+#pragma unroll
+    for (int k = 0; k < MOM_PER_THREAD; ++k) {
+        const int t = t0 + k * 256;
+        if (t < width) out[t] = acc[k];
     }
 }
 
 __global__ void k_moments_final(const double* part, int nblk, int width, double* out) {
-    for (int t = threadIdx.x; t < width; t += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * width + t];
-        out[t] = s;
-    }
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= width) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * width + t];
+    out[t] = s;
 }
 
 size_t moments_part_doubles(int64_t n, int d) { return (size_t)((n + 511) / 512) * (2 + d * d + d); }
@@ -395,8 +428,10 @@ hipError_t launch_moments(const float* X, int64_t n, int d, const float* w, doub
     const int rows_per_blk = 512;
     const int nblk = (int)((n + rows_per_blk - 1) / rows_per_blk);
     const int width = 2 + d * d + d;
-    hipLaunchKernelGGL(k_moments_part, dim3(nblk), dim3(256), 0, stream, X, n, d, w, part, rows_per_blk);
-    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(256), 0, stream, part, nblk, width, out);
+    const int oblk = (width + MOM_OUT_BLK - 1) / MOM_OUT_BLK;
+    hipLaunchKernelGGL(k_moments_part, dim3(nblk, oblk), dim3(256), (size_t)MOM_CHUNK * d * sizeof(float), stream, X,
+                       n, d, w, part, rows_per_blk);
+    hipLaunchKernelGGL(k_moments_final, dim3((width + 255) / 256), dim3(256), 0, stream, part, nblk, width, out);
     return hipGetLastError();
 }
 

@@ -329,6 +329,10 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
     GW_HIP(gwk::launch_norms_logw(X_, n, n_pad_, D_, a, asum, xn_, la2_, st_));
     GW_HIP(gwk::launch_norms_logw(Y_, m, m_pad_, E_, b, bsum, ym_, lb2_, st_));
     if (pwY_) GW_HIP(gwk::launch_pack_payload(Y_, m, m_pad_, E_, pwY_, st_));
+    // moments of the features for C(alpha, beta) of Lemma C.1 (and the
+    // gradients); they depend on X, Y and the weights only
+    GW_HIP(gwk::launch_moments(X_, n, D_, a, mompart_, momx_, st_));
+    GW_HIP(gwk::launch_moments(Y_, m, E_, b, mompart_, momy_, st_));
 
     // initial state
     if (gamma0) {
@@ -633,9 +637,6 @@ Status Solve::finish_enqueue(gw_result* out) {
     GW_HIP(gwk::launch_check_final(r64, kl64, n_, a_, c64, m_, b_, asum_, bsum_, scal_, st_));
     c_.prof.end(st_);
     c_.prof.entries = n_ * m_;
-    // moments for C(alpha, beta)
-    GW_HIP(gwk::launch_moments(X_, n_, D_, a_, mompart_, momx_, st_));
-    GW_HIP(gwk::launch_moments(Y_, m_, E_, b_, mompart_, momy_, st_));
     // outputs: potentials back in Algorithm 1's convention (cost units)
     if (geo_.path == 1) {
         if (out->f) GW_HIP(gwk::launch_epilogue(n_, U_[pa_], Ul_[pa_], la2_, nullptr, nullptr, 0, kappa_, out->f, st_));

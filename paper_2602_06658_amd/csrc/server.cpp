@@ -277,11 +277,17 @@ void drop_all_active(gw_server* s, ReqState st, gw_status code, const std::strin
 void round_main(gw_server* s) {
     (void)hipSetDevice(s->base->device);
     hipStream_t main = s->base->stream;
-    hipEvent_t pace[2] = {nullptr, nullptr};
-    (void)hipEventCreateWithFlags(&pace[0], hipEventDisableTiming);
-    (void)hipEventCreateWithFlags(&pace[1], hipEventDisableTiming);
+    // rounds in flight: deep enough that small rounds (few, small requests)
+    // do not leave the GPU waiting for launches, shallow enough that new
+    // arrivals join within a few rounds
+    constexpr int PACE = 3;
+    hipEvent_t pace[PACE];
+    bool pace_used[PACE];
+    for (int k = 0; k < PACE; ++k) {
+        (void)hipEventCreateWithFlags(&pace[k], hipEventDisableTiming);
+        pace_used[k] = false;
+    }
     int pi = 0;
-    bool pace_used[2] = {false, false};
     bool busy = false;
     Clock::time_point busy_from;
     for (;;) {
@@ -355,10 +361,9 @@ void round_main(gw_server* s) {
                     complete(s, q, RQ_FAILED, fs.good() ? GW_EDEVICE : fs.code, fs.good() ? "event" : fs.msg);
                 }
             }
-            // keep at most two rounds in flight so that arrivals join promptly
             (void)hipEventRecord(pace[pi], main);
             pace_used[pi] = true;
-            pi ^= 1;
+            pi = (pi + 1) % PACE;
             if (pace_used[pi]) (void)hipEventSynchronize(pace[pi]);
         } else if (!s->finishing.empty()) {
             (void)hipEventSynchronize(s->finishing.front()->slot->ev);
@@ -385,8 +390,7 @@ void round_main(gw_server* s) {
     }
     s->finishing.clear();
     drop_all_active(s, RQ_CANCELLED, GW_ECANCELLED, "server stopped");
-    (void)hipEventDestroy(pace[0]);
-    (void)hipEventDestroy(pace[1]);
+    for (int k = 0; k < PACE; ++k) (void)hipEventDestroy(pace[k]);
 }
 
 void cancel_unstarted(gw_server* s, Request* q) {
