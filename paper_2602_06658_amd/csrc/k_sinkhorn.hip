@@ -46,102 +46,185 @@ struct PassArgs {
 // Stabilised MFMA pass
 // ---------------------------------------------------------------------------
 
-template <class C, int RW>
-__device__ __forceinline__ void pass_stab_body(const PassArgs& p, int wg) {
-    if (!should_run(p.ctl, p.run_if)) return;
-    constexpr int NU = C::UNITS * 64;
-    __shared__ uint4 zbuf[2][NU];
-    extern __shared__ float dyn[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int rb, cb;
-    tile_coords(wg, p.n_mt_r, p.n_mt_c, rb, cb);
-    const int c0 = cb * p.bc_chunks;
-    const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
-    const int bcw = p.bc_chunks * 32;
-    float* colacc = dyn + wave * bcw;
-    for (int i = lane; i < nch * 32; i += 64) colacc[i] = 0.f;
-
-    ChunkStage<NU> st;
-    st.load(p.B + (size_t)c0 * NU, tid);
-    st.store(zbuf[0], tid);
-    __syncthreads();
-
-    typename C::A a[RW];
-    float racc[RW][16];
-    bool act[RW];
-    int rchunk0 = 0;
-    const int total = p.rg * nch;
-    for (int it = 0; it < total; ++it) {
-        const int g = it / nch, cc = it - g * nch;
-        if (cc == 0) {
-            rchunk0 = (rb * p.rg + g) * (WAVES * RW) + wave * RW;
-#pragma unroll
-            for (int t = 0; t < RW; ++t) {
-                act[t] = rchunk0 + t < p.n_chunks_r;
-                if (act[t]) C::load(a[t], p.A, rchunk0 + t, lane);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) racc[t][q] = 0.f;
-            }
-            // complete the row-operand loads here, once per row group, so
-            // the tiles below never wait on the in-flight chunk prefetch
-            wait_vmem_all();
-        }
-        const bool has_next = it + 1 < total;
-        if (has_next) st.load(p.B + (size_t)(c0 + (it + 1) % nch) * NU, tid);
-        const uint4* zb = zbuf[it & 1];
-        float cs = -0.0f;  // exact identity for the first add
-        if (act[RW - 1]) {
-            // all row tiles of this wave in range (every wave but the last
-            // one of the last row group): no per-tile branches, the column
-            // fragment is read from LDS once and the tiles interleave
-            typename C::B b;
-            C::load_b(b, zb, lane);
-            f32x16_t s[RW];
-#pragma unroll
-            for (int t = 0; t < RW; ++t) s[t] = C::tile_ab(a[t], b);
-#pragma unroll
-            for (int t = 0; t < RW; ++t)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const float e = fast_exp2(s[t][q]);
-                    racc[t][q] += e;
-                    cs += e;
-                }
-        } else {
-#pragma unroll
-            for (int t = 0; t < RW; ++t) {
-                if (act[t]) {
-                    f32x16_t s = C::tile(a[t], zb, lane);
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const float e = fast_exp2(s[q]);
-                        racc[t][q] += e;
-                        cs += e;
-                    }
-                }
-            }
-        }
-        cs += shfl_xor_f(cs, 32);
-        if (lane < 32) colacc[cc * 32 + lane] += cs;
-        if (cc == nch - 1) {
-#pragma unroll
-            for (int t = 0; t < RW; ++t) {
-                if (act[t]) {
-                    const float tot = half_transpose_sum16(racc[t], lane);
-                    if (!(lane & 16))
-                        p.rp[(size_t)cb * p.n_pad + (rchunk0 + t) * 32 + acc_row(lane & 15, lane)] = tot;
-                }
-            }
-        }
-        if (has_next) st.store(zbuf[(it + 1) & 1], tid);
-        __syncthreads();
-    }
+// Column partials (the per-wave accumulators summed in wave order) and the
+// macro tile's row partials from LDS to the partial buffers.
+template <int RW>
+__device__ __forceinline__ void pass_stab_store(const PassArgs& p, const float* dyn, int rb, int cb, int c0,
+                                                int nch) {
+    const int tid = threadIdx.x, bcw = p.bc_chunks * 32;
+    const float* rowacc = dyn + WAVES * bcw;
     for (int i = tid; i < nch * 32; i += THREADS) {
         float s = 0.f;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) s += dyn[w * bcw + i];
         p.cp[(size_t)rb * p.m_pad + c0 * 32 + i] = s;
     }
+    const int rows = p.rg * WAVES * RW * 32;
+    const int row0 = rb * rows;
+    const int nrows = min(rows, p.n_chunks_r * 32 - row0);
+    for (int i = tid; i < nrows; i += THREADS) p.rp[(size_t)cb * p.n_pad + row0 + i] = rowacc[i];
+}
+
+// One exponent tile set of a stabilised step: 2^s for the wave's RW row
+// tiles against one column chunk, accumulated into the row sums (racc) and
+// returned summed over the chunk's rows (lanes l and l + 32 hold column l).
+template <class C, int RW>
+__device__ __forceinline__ float stab_exp_sums(const f32x16_t (&s)[RW], float (&racc)[RW][16], int nact) {
+    float cs = -0.0f;  // exact identity for the first add
+#pragma unroll
+    for (int t = 0; t < RW; ++t)
+        if (t < nact) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const float e = fast_exp2(s[t][q]);
+                racc[t][q] += e;
+                cs += e;
+            }
+        }
+    return cs + shfl_xor_f(cs, 32);
+}
+
+// Column chunks of a full macro tile (every row tile in range, even chunk
+// count) stream through an LDS ring filled by LDS-direct loads: one L2 read
+// per chunk per work-group, nothing staged in registers.  Chunks go in
+// pairs with one barrier per pair; RING_AHEAD pairs beyond the current one
+// are in flight.  Wave w moves slabs w, w + WAVES, ... (mod UNITS), the same
+// number for every wave, so that each wave counts its own loads.
+constexpr int RING_MAX_UNITS = 9;
+constexpr int RING_AHEAD = 1;
+template <class C, int RW>
+__device__ __forceinline__ void stab_ring_tile(const PassArgs& p, int rb, int c0, int nch, int wave, int lane,
+                                               float* colacc, float* rowacc) {
+    constexpr int NU = C::UNITS * 64;
+    constexpr int RING = 2 * (RING_AHEAD + 1), PW = (C::UNITS + WAVES - 1) / WAVES;
+    __shared__ uint4 ring[RING * NU];
+    auto issue = [&](int k) {
+        const uint4* src = p.B + (size_t)(c0 + k % nch) * NU;
+        uint4* dst = ring + (k % RING) * NU;
+#pragma unroll
+        for (int u = 0; u < PW; ++u) {
+            const int sl = (wave + u * WAVES) % C::UNITS;
+            __builtin_amdgcn_global_load_lds(src + sl * 64 + lane,
+                                             (__attribute__((address_space(3))) void*)(dst + sl * 64), 16, 0, 0);
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < 2 * RING_AHEAD; ++k) issue(k);
+    typename C::A a[RW];
+    float racc[RW][16];
+    for (int g = 0; g < p.rg; ++g) {
+        const int rchunk0 = (rb * p.rg + g) * (WAVES * RW) + wave * RW;
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+            C::load(a[t], p.A, rchunk0 + t, lane);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) racc[t][q] = 0.f;
+        }
+        const int k0 = g * nch;
+        auto step = [&](int cc) {
+            typename C::B b;
+            C::load_b(b, ring + ((k0 + cc) % RING) * NU, lane);
+            f32x16_t s[RW];
+#pragma unroll
+            for (int t = 0; t < RW; ++t) s[t] = C::tile_ab(a[t], b);
+            const float cs = stab_exp_sums<C, RW>(s, racc, RW);
+            if (lane < 32) colacc[cc * 32 + lane] += cs;
+        };
+        for (int cc = 0; cc < nch; cc += 2) {
+            // this wave's loads of the pair have landed (only the
+            // RING_AHEAD - 1 pairs issued after them may be in flight; at a
+            // row group's start everything, with the row operand); after the
+            // barrier every wave's have, and every wave is done with the pair
+            // before, whose slots the next loads reuse.  Positions past the
+            // tile's end reload chunks that are never read.
+            if (cc == 0)
+                wait_vmem_all();
+            else
+                wait_vmem<2 * PW * (RING_AHEAD - 1)>();
+            barrier_only();
+            issue(k0 + cc + 2 * RING_AHEAD);
+            issue(k0 + cc + 2 * RING_AHEAD + 1);
+            step(cc);
+            step(cc + 1);
+        }
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+            const float tot = half_transpose_sum16(racc[t], lane);
+            if (!(lane & 16)) rowacc[((g * WAVES + wave) * RW + t) * 32 + acc_row(lane & 15, lane)] = tot;
+        }
+    }
+}
+
+// Stabilised pass over one macro tile.  Full macro tiles of cores up to
+// RING_MAX_UNITS units take the LDS ring above.  Other tiles (the last row
+// of macro tiles, a last column tile with an odd chunk count, wide cores)
+// read each wave's column fragments straight from the pack, one chunk ahead
+// in registers (loaded once this chunk's MFMAs have read them), with
+// per-tile bounds.  Row partials go to LDS and are stored with the column
+// partials after the loop.
+template <class C, int RW>
+__device__ __forceinline__ void pass_stab_body(const PassArgs& p, int wg) {
+    if (!should_run(p.ctl, p.run_if)) return;
+    constexpr int NU = C::UNITS * 64;
+    extern __shared__ float dyn[];
+    // the wave index through readfirstlane: row-tile bounds derived from it
+    // are known to be wave-uniform and branch with scalar branches
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int rb, cb;
+    tile_coords(wg, p.n_mt_r, p.n_mt_c, rb, cb);
+    const int c0 = cb * p.bc_chunks;
+    const int nch = min(p.bc_chunks, p.n_chunks_c - c0);
+    const int bcw = p.bc_chunks * 32;
+    float* colacc = dyn + wave * bcw;
+    float* rowacc = dyn + WAVES * bcw;
+    for (int i = lane; i < nch * 32; i += 64) colacc[i] = 0.f;
+
+    // full macro tiles: every row tile in range, even chunk count
+    const bool full = (rb + 1) * p.rg * WAVES * RW <= p.n_chunks_r && (nch & 1) == 0;
+    bool done = false;
+    if constexpr (C::UNITS <= RING_MAX_UNITS) {
+        if (full) {
+            stab_ring_tile<C, RW>(p, rb, c0, nch, wave, lane, colacc, rowacc);
+            done = true;
+        }
+    }
+    if (!done) {
+        auto chunk_ptr = [&](int k) { return p.B + (size_t)(c0 + k % nch) * NU; };
+        typename C::A a[RW];
+        float racc[RW][16];
+        typename C::B b;
+        C::load_b(b, chunk_ptr(0), lane);
+        for (int g = 0; g < p.rg; ++g) {
+            const int rchunk0 = (rb * p.rg + g) * (WAVES * RW) + wave * RW;
+            const int nact = min(RW, p.n_chunks_r - rchunk0);  // wave-uniform
+            if (nact <= 0) break;
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                if (t < nact) C::load(a[t], p.A, rchunk0 + t, lane);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) racc[t][q] = 0.f;
+            }
+            wait_vmem_all();
+            for (int cc = 0; cc < nch; ++cc) {
+                f32x16_t s[RW];
+#pragma unroll
+                for (int t = 0; t < RW; ++t)
+                    if (t < nact) s[t] = C::tile_ab(a[t], b);
+                C::load_b(b, chunk_ptr(g * nch + cc + 1), lane);
+                const float cs = stab_exp_sums<C, RW>(s, racc, nact);
+                if (lane < 32) colacc[cc * 32 + lane] += cs;
+            }
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                if (t < nact) {
+                    const float tot = half_transpose_sum16(racc[t], lane);
+                    if (!(lane & 16)) rowacc[((g * WAVES + wave) * RW + t) * 32 + acc_row(lane & 15, lane)] = tot;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    pass_stab_store<RW>(p, dyn, rb, cb, c0, nch);
 }
 
 
@@ -551,6 +634,13 @@ static PassArgs make_pass_args(const Operands& op, const Geometry& g, const Part
     return a;
 }
 
+// Dynamic LDS of a pass launch: per-wave column accumulators (three arrays in
+// the safe pass), plus the macro tile's row partials in the stabilised pass.
+static size_t pass_lds_bytes(const Geometry& g, int safe) {
+    const size_t cols = (size_t)WAVES * g.bc_chunks * 32;
+    return (safe ? 3 * cols : cols + (size_t)g.rg * g.rows_per_group) * sizeof(float);
+}
+
 template <class C, int RW>
 static hipError_t launch_mfma_batch(const PassBatch& b, size_t lds, int safe, hipStream_t stream) {
     if (safe)
@@ -607,7 +697,7 @@ hipError_t launch_pass_batch(const PassItem* items, int n, int run_if, int safe,
             if (p2 != prec || pack_units(it.op.prec, it.op.d) != units) break;
             b.req[b.n] = make_pass_args(it.op, it.g, it.pp, it.ctl, run_if);
             b.start[b.n + 1] = b.start[b.n] + it.g.n_mt_r * it.g.n_mt_c;
-            const size_t l = (size_t)(safe ? 3 : 1) * WAVES * it.g.bc_chunks * 32 * sizeof(float);
+            const size_t l = pass_lds_bytes(it.g, safe);
             lds = l > lds ? l : lds;
             ++b.n;
             ++g0;
@@ -639,7 +729,7 @@ static hipError_t launch_mfma(const Operands& op, const Geometry& g, const Parti
     a.n_pad = g.n_pad;
     a.m_pad = g.m_pad;
     const int grid = g.n_mt_r * g.n_mt_c;
-    const size_t lds = (size_t)(safe ? 3 : 1) * WAVES * g.bc_chunks * 32 * sizeof(float);
+    const size_t lds = pass_lds_bytes(g, safe);
     if (safe)
         hipLaunchKernelGGL((k_pass_safe<C, RW>), dim3(grid), dim3(THREADS), lds, stream, a);
     else
@@ -674,7 +764,7 @@ static hipError_t launch_valu_d(const Operands& op, const Geometry& g, const Par
     a.n_mt_r = g.n_mt_r;
     a.n_mt_c = g.n_mt_c;
     const int grid = g.n_mt_r * g.n_mt_c;
-    const size_t lds = (size_t)(safe ? 3 : 1) * WAVES * g.bc_chunks * 32 * sizeof(float);
+    const size_t lds = pass_lds_bytes(g, safe);
     if (safe)
         hipLaunchKernelGGL((k_pass_valu<D, 1>), dim3(grid), dim3(THREADS), lds, stream, a);
     else

@@ -114,3 +114,31 @@ def test_valu_path_small_dims(gw):
     rel = abs(res["loss_lift"] - ref_loss) / abs(ref_loss)
     print("valu rel", rel, "gamma", np.abs(res["gamma"].cpu().numpy() - ref.gamma).max())
     assert rel < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_repeatable_bitwise(gw, prec):
+    """The same solve twice, with a solve of another size in between, gives
+    bitwise equal potentials, map and loss: the passes and reductions run in
+    a fixed order.  8192 x 7900 at D = 64 covers full macro tiles, a last
+    row of partial ones and a last column tile with an odd chunk count."""
+    from workloads import scale_features, seeded_gamma
+
+    x, y = dev(scale_features(71, 8192, 64)), dev(scale_features(72, 7900, 64))
+    a = dev(np.full(8192, 1.0 / 8192))
+    b = dev(np.full(7900, 1.0 / 7900))
+    g0 = dev(seeded_gamma(73, 64, 64))
+    ctx = gw.Context()
+    ctx.set_penalty(2, "features")
+
+    def run(xx, aa, yy, bb):
+        return ctx.solve(xx, aa, yy, bb, 1.0, 0.5, 2, 30, precision=prec, gamma0=g0)
+
+    r1 = run(x, a, y, b)
+    run(y[:5000], b[:5000] / b[:5000].sum(), x[:6000], a[:6000] / a[:6000].sum())
+    r2 = run(x, a, y, b)
+    print(prec, "loss", r1["loss_lift"], "safe iters", r1["safe_iters"])
+    assert r1["safe_iters"] < 2 * 30  # the stabilised pass ran
+    for k in ("f", "g", "gamma"):
+        assert torch.equal(r1[k], r2[k]), k
+    assert r1["loss_lift"] == r2["loss_lift"]
