@@ -830,6 +830,8 @@ struct CombineDev {
 
 // blk / nblk: this block's index among the problem's nblk blocks (the last
 // one to finish takes the mode decision)
+constexpr int COMBINE_UNROLL = 16;
+
 __device__ __forceinline__ void combine_body(const CombineDev& cd, int* ctl, int run_if, int blk, int nblk) {
     const CombineArgs& a = cd.a;
     if (!should_run(ctl, run_if)) return;
@@ -837,55 +839,104 @@ __device__ __forceinline__ void combine_body(const CombineDev& cd, int* ctl, int
     const int user = ctl[CTL_USER];
     const bool safe_parts = a.is_retry || mode == MODE_SAFE;
     const bool check_stab = !a.is_retry && mode == MODE_STAB && user != 2;
-    const int nrow = a.do_rows ? a.n : 0;
+    // each thread merges four consecutive rows (or columns): one 16-byte
+    // load per partial tile; the partials are merged in tile order and their
+    // loads issued a block at a time so that many are in flight
+    const int nrow4 = a.do_rows ? (a.n + 3) / 4 : 0;
+    const int ncol4 = a.do_cols ? (a.m + 3) / 4 : 0;
     const int idx = blk * blockDim.x + threadIdx.x;
     int bad = 0, unsafe = 0, numeric = 0;
-    if (idx < nrow + (a.do_cols ? a.m : 0)) {
-        const bool is_row = idx < nrow;
-        const int i = is_row ? idx : idx - nrow;
+    if (idx < nrow4 + ncol4) {
+        const bool is_row = idx < nrow4;
+        const int i0 = 4 * (is_row ? idx : idx - nrow4);
+        const int cnt = min(4, (is_row ? a.n : a.m) - i0);
         const int npart = is_row ? a.n_mt_c : a.n_mt_r;
-        const int stride = is_row ? a.n_pad : a.m_pad;
-        const float* p1 = is_row ? a.rp : a.cp;
-        const float* p2 = is_row ? a.rp2 : a.cp2;
-        float l2;
-        double l2d;
+        const size_t stride4 = (size_t)(is_row ? a.n_pad : a.m_pad) / 4;
+        const float4* q1 = reinterpret_cast<const float4*>((is_row ? a.rp : a.cp) + i0);
+        const float4* q2 = reinterpret_cast<const float4*>((is_row ? a.rp2 : a.cp2) + i0);
+        double l2d[4];
+        int k = 0;
         if (!safe_parts) {
-            float s = 0.f;
-            for (int k = 0; k < npart; ++k) s += p1[(size_t)k * stride + i];
-            l2d = log2((double)s);
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (; k + COMBINE_UNROLL <= npart; k += COMBINE_UNROLL) {
+                float4 v[COMBINE_UNROLL];
+#pragma unroll
+                for (int u = 0; u < COMBINE_UNROLL; ++u) v[u] = q1[(k + u) * stride4];
+#pragma unroll
+                for (int u = 0; u < COMBINE_UNROLL; ++u) {
+                    acc.x += v[u].x;
+                    acc.y += v[u].y;
+                    acc.z += v[u].z;
+                    acc.w += v[u].w;
+                }
+            }
+            for (; k < npart; ++k) {
+                const float4 v = q1[k * stride4];
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
+            }
+            l2d[0] = log2((double)acc.x);
+            l2d[1] = log2((double)acc.y);
+            l2d[2] = log2((double)acc.z);
+            l2d[3] = log2((double)acc.w);
         } else {
-            float M = -3.0e38f, S = 0.f;
-            for (int k = 0; k < npart; ++k) lse_merge(M, S, p1[(size_t)k * stride + i], p2[(size_t)k * stride + i]);
-            l2d = (double)M + log2((double)S);
-        }
-        l2 = (float)l2d;
-        const float lw = is_row ? a.la2[i] : a.lb2[i];
-        const float lr = l2 - lw;
-        const bool fin = isfinite(lr);
-        if (check_stab && (!fin || fabsf(lr) > STAB_LIMIT)) bad = 1;
-        if (!fin && !check_stab) numeric = 1;
-        if (!fin || fabsf(lr) > COMFORT_LIMIT) unsafe = 1;
-        // potentials are FP32 (hi, lo) pairs; the update itself runs in FP64
-        const double cur = is_row ? join_df(a.U_cur[i], a.Ul_cur[i]) : join_df(a.V_cur[i], a.Vl_cur[i]);
-        const double lr64 = (double)l2d - (double)lw;
-        const double nxt = fin ? cur - (double)a.step * lr64 : cur;
-        float nh, nl;
-        split_df(nxt, nh, nl);
-        if (is_row) {
-            a.U_next[i] = nh;
-            a.Ul_next[i] = nl;
-        } else {
-            a.V_next[i] = nh;
-            a.Vl_next[i] = nl;
+            float M[4] = {-3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f}, S[4] = {0.f, 0.f, 0.f, 0.f};
+            constexpr int U2 = COMBINE_UNROLL / 2;
+            auto merge4 = [&](const float4& vm, const float4& vs) {
+                lse_merge(M[0], S[0], vm.x, vs.x);
+                lse_merge(M[1], S[1], vm.y, vs.y);
+                lse_merge(M[2], S[2], vm.z, vs.z);
+                lse_merge(M[3], S[3], vm.w, vs.w);
+            };
+            for (; k + U2 <= npart; k += U2) {
+                float4 vm[U2], vs[U2];
+#pragma unroll
+                for (int u = 0; u < U2; ++u) {
+                    vm[u] = q1[(k + u) * stride4];
+                    vs[u] = q2[(k + u) * stride4];
+                }
+#pragma unroll
+                for (int u = 0; u < U2; ++u) merge4(vm[u], vs[u]);
+            }
+            for (; k < npart; ++k) merge4(q1[k * stride4], q2[k * stride4]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) l2d[c] = (double)M[c] + log2((double)S[c]);
         }
         void* pack = is_row ? a.packA_next : a.packB_next;
-        if (pack) {
-            if (a.prec == PREC_F32) {
-                if (is_row) write_pot_a_f32((float*)pack, i, cd.kb, cd.units, nh, nl);
-                else write_pot_b_f32((float*)pack, i, cd.kb, cd.units, nh, nl);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= cnt) break;
+            const int i = i0 + c;
+            const float l2 = (float)l2d[c];
+            const float lw = is_row ? a.la2[i] : a.lb2[i];
+            const float lr = l2 - lw;
+            const bool fin = isfinite(lr);
+            if (check_stab && (!fin || fabsf(lr) > STAB_LIMIT)) bad = 1;
+            if (!fin && !check_stab) numeric = 1;
+            if (!fin || fabsf(lr) > COMFORT_LIMIT) unsafe = 1;
+            // potentials are FP32 (hi, lo) pairs; the update itself runs in FP64
+            const double cur = is_row ? join_df(a.U_cur[i], a.Ul_cur[i]) : join_df(a.V_cur[i], a.Vl_cur[i]);
+            const double lr64 = l2d[c] - (double)lw;
+            const double nxt = fin ? cur - (double)a.step * lr64 : cur;
+            float nh, nl;
+            split_df(nxt, nh, nl);
+            if (is_row) {
+                a.U_next[i] = nh;
+                a.Ul_next[i] = nl;
             } else {
-                if (is_row) write_pot_a_bf16((uint16_t*)pack, i, cd.kb, cd.units, nh, nl);
-                else write_pot_b_bf16((uint16_t*)pack, i, cd.kb, cd.units, nh, nl);
+                a.V_next[i] = nh;
+                a.Vl_next[i] = nl;
+            }
+            if (pack) {
+                if (a.prec == PREC_F32) {
+                    if (is_row) write_pot_a_f32((float*)pack, i, cd.kb, cd.units, nh, nl);
+                    else write_pot_b_f32((float*)pack, i, cd.kb, cd.units, nh, nl);
+                } else {
+                    if (is_row) write_pot_a_bf16((uint16_t*)pack, i, cd.kb, cd.units, nh, nl);
+                    else write_pot_b_bf16((uint16_t*)pack, i, cd.kb, cd.units, nh, nl);
+                }
             }
         }
     }
@@ -951,7 +1002,7 @@ static CombineDev make_combine_dev(const CombineArgs& a) {
 }
 
 static int combine_blocks(const CombineArgs& a) {
-    const int total = (a.do_rows ? a.n : 0) + (a.do_cols ? a.m : 0);
+    const int total = (a.do_rows ? (a.n + 3) / 4 : 0) + (a.do_cols ? (a.m + 3) / 4 : 0);
     return (total + 255) / 256;
 }
 
