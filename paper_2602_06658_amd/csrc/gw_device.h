@@ -24,13 +24,6 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 // s_waitcnt vmcnt(0) with expcnt and lgkmcnt left at their maxima (gfx9
 // encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 __device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-// Wait until at most N vector memory operations of this wave are in flight
-// (loads complete in issue order).
-template <int N>
-__device__ __forceinline__ void wait_vmem() {
-    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
-    __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
-}
 // Work-group barrier without the memory fence of __syncthreads(), for
 // callers that have already waited for what the other waves must see.  The
 // empty asm statements keep the compiler from moving memory accesses across.

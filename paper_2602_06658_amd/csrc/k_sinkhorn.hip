@@ -85,31 +85,25 @@ __device__ __forceinline__ float stab_exp_sums(const f32x16_t (&s)[RW], float (&
 }
 
 // Column chunks of a full macro tile (every row tile in range, even chunk
-// count) stream through an LDS ring filled by LDS-direct loads: one L2 read
-// per chunk per work-group, nothing staged in registers.  Chunks go in
-// pairs with one barrier per pair; RING_AHEAD pairs beyond the current one
-// are in flight.  Wave w moves slabs w, w + WAVES, ... (mod UNITS), the same
-// number for every wave, so that each wave counts its own loads.
+// count) stream through a 4-slot LDS ring filled by LDS-direct loads: one L2
+// read per chunk per work-group, nothing staged in registers.  Chunks go in
+// pairs with one barrier per pair, the next pair in flight.  Wave w moves
+// slabs w, w + WAVES, ... of each chunk.
 constexpr int RING_MAX_UNITS = 9;
-constexpr int RING_AHEAD = 1;
 template <class C, int RW>
 __device__ __forceinline__ void stab_ring_tile(const PassArgs& p, int rb, int c0, int nch, int wave, int lane,
                                                float* colacc, float* rowacc) {
-    constexpr int NU = C::UNITS * 64;
-    constexpr int RING = 2 * (RING_AHEAD + 1), PW = (C::UNITS + WAVES - 1) / WAVES;
+    constexpr int NU = C::UNITS * 64, RING = 4;
     __shared__ uint4 ring[RING * NU];
     auto issue = [&](int k) {
         const uint4* src = p.B + (size_t)(c0 + k % nch) * NU;
         uint4* dst = ring + (k % RING) * NU;
-#pragma unroll
-        for (int u = 0; u < PW; ++u) {
-            const int sl = (wave + u * WAVES) % C::UNITS;
+        for (int sl = wave; sl < C::UNITS; sl += WAVES)
             __builtin_amdgcn_global_load_lds(src + sl * 64 + lane,
                                              (__attribute__((address_space(3))) void*)(dst + sl * 64), 16, 0, 0);
-        }
     };
-#pragma unroll
-    for (int k = 0; k < 2 * RING_AHEAD; ++k) issue(k);
+    issue(0);
+    issue(1);
     typename C::A a[RW];
     float racc[RW][16];
     for (int g = 0; g < p.rg; ++g) {
@@ -131,19 +125,15 @@ __device__ __forceinline__ void stab_ring_tile(const PassArgs& p, int rb, int c0
             if (lane < 32) colacc[cc * 32 + lane] += cs;
         };
         for (int cc = 0; cc < nch; cc += 2) {
-            // this wave's loads of the pair have landed (only the
-            // RING_AHEAD - 1 pairs issued after them may be in flight; at a
-            // row group's start everything, with the row operand); after the
-            // barrier every wave's have, and every wave is done with the pair
-            // before, whose slots the next loads reuse.  Positions past the
-            // tile's end reload chunks that are never read.
-            if (cc == 0)
-                wait_vmem_all();
-            else
-                wait_vmem<2 * PW * (RING_AHEAD - 1)>();
+            // this wave's loads of the pair (and at a row group's start the
+            // row operand) have landed; after the barrier every wave's have,
+            // and every wave is done with the pair before, whose slots the
+            // next loads reuse.  Positions past the tile's end reload chunks
+            // that are never read.
+            wait_vmem_all();
             barrier_only();
-            issue(k0 + cc + 2 * RING_AHEAD);
-            issue(k0 + cc + 2 * RING_AHEAD + 1);
+            issue(k0 + cc + 2);
+            issue(k0 + cc + 3);
             step(cc);
             step(cc + 1);
         }
