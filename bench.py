@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--serve-landmarks", type=int, default=512)
     ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of capacity")
+    ap.add_argument("--serve-sweep", default="",
+                    help="extra arrival rates (fractions of capacity, comma-separated) replayed through the "
+                         "batching server, e.g. 0.5,0.9,1.1")
     return ap.parse_args()
 
 
@@ -165,11 +168,16 @@ def serve_bench(args, gwm, torch, dev) -> dict:
     gaps = arrivals / rate  # the trace is a unit-rate Poisson process
     batched = run(args.serve_slots, gaps)
     single = run(1, gaps)
-    return {"workload": f"{len(reqs)} requests, N, M log-uniform in [1e3, 5e4], d in {{2, 3}}, |x-x'| lifted to "
-                        f"D=32 ({args.serve_landmarks} landmarks), eps 0.01, 20x50, {args.serve_precision}",
-            "capacity_solves_per_s": cap["solves_per_s"], "capacity_entries_per_s": cap["entries_per_s"],
-            "arrival_rate_per_s": rate, "batched": batched, "one_at_a_time": single,
-            "slots": args.serve_slots}
+    out = {"workload": f"{len(reqs)} requests, N, M log-uniform in [1e3, 5e4], d in {{2, 3}}, |x-x'| lifted to "
+                       f"D=32 ({args.serve_landmarks} landmarks), eps 0.01, 20x50, {args.serve_precision}",
+           "capacity_solves_per_s": cap["solves_per_s"], "capacity_entries_per_s": cap["entries_per_s"],
+           "arrival_rate_per_s": rate, "batched": batched, "one_at_a_time": single,
+           "slots": args.serve_slots}
+    loads = [float(v) for v in args.serve_sweep.split(",") if v.strip()]
+    if loads:
+        out["sweep"] = {f"{ld:g}": dict(run(args.serve_slots, arrivals / (ld * cap["solves_per_s"])),
+                                        arrival_rate_per_s=ld * cap["solves_per_s"]) for ld in loads}
+    return out
 
 
 def cpu_baseline(prob, n_sample: int, iters: int) -> dict:
