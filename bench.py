@@ -159,9 +159,13 @@ def serve_bench(args, gwm, torch, dev) -> dict:
         wall = time.perf_counter() - t0
         srv.close()
         lat = np.array([o["latency_s"] for o in outs])
-        return {"solves_per_s": len(reqs) / wall, "wall_s": wall, "entries_per_s": work / wall,
-                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-                "max_marginal_err": float(max(o["marginal_err"] for o in outs))}
+        res = {"solves_per_s": len(reqs) / wall, "wall_s": wall, "entries_per_s": work / wall,
+               "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+               "max_marginal_err": float(max(o["marginal_err"] for o in outs))}
+        print(f"serving: {slots} slot(s), {'open loop' if gaps is not None else 'all at once'}: "
+              f"{res['solves_per_s']:.2f} solves/s, p50 {res['p50_latency_s']:.3f} s, "
+              f"p99 {res['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
+        return res
 
     cap = run(args.serve_slots, None)
     rate = args.serve_load * cap["solves_per_s"]
