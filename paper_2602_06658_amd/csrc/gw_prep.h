@@ -76,11 +76,12 @@ hipError_t launch_cov_reduce(const CovOut& in, int n_mt_c, int64_t n, int64_t n_
 hipError_t launch_gamma_final(const double* part, int64_t n, int dx, int dw, const float* gamma_old, double* gamma64,
                               float* gamma32, double* scal, hipStream_t stream);
 
-// FP64 evaluation of the coupling defined by the packed operands.  Row pass:
-// r64_i = sum_j pi_ij and kl_i = ln2 sum_j pi_ij (s_ij - log2 a_i - log2 b_j);
-// column pass (operands swapped): c64_j.
-hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols, int64_t n, int64_t n_pad, int64_t m,
-                          int64_t m_pad, const float* la2, const float* lb2, double* rsum, double* kl,
+// FP64 evaluation of the coupling defined by the packed operands, one sweep:
+// r64_i = sum_j pi_ij, kl_i = ln2 sum_j pi_ij (s_ij - log2 a_i - log2 b_j),
+// c64_j = sum_i pi_ij.  `part` holds check64_part_doubles(n, m) doubles.
+size_t check64_part_doubles(int64_t n, int64_t m);
+hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols, int64_t n, int64_t m,
+                          const float* la2, const float* lb2, double* part, double* r64, double* kl, double* c64,
                           hipStream_t stream);
 hipError_t launch_check64_direct(int d, const float* X, const float* xn, const float* U, const float* Ul,
                                  const float* Z, const float* zm, const float* V, const float* Vl, float kappa,

@@ -721,8 +721,10 @@ hipError_t launch_gamma_final(const double* part, int64_t n, int dx, int dw, con
 
 // ---------------------------------------------------------------------------
 // FP64 check: s_ij = sum_k A_ik B_jk evaluated exactly in FP64 from the
-// packed operands (the coupling the passes iterate), pi = 2^s.
-// Thread = row; columns staged in LDS 32 at a time; K in slabs of 16.
+// packed operands (the coupling the passes iterate), pi = 2^s.  One sweep
+// over the entries gives the row sums, the row KL terms and the column sums:
+// each work-group takes a CKM x CKM macro tile and writes per-tile partials,
+// which a second kernel adds up in tile order.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ float pack_elem(const void* pack, int prec, int units, int row, int k) {
@@ -730,100 +732,160 @@ __device__ __forceinline__ float pack_elem(const void* pack, int prec, int units
     return bf16_bits_to_f32(((const uint16_t*)pack)[bf16_pack_off(row, k, units)]);
 }
 
-// 64 x 64 tiles of (row, column) entries; K consumed in blocks of 32
-// decoded to float in LDS; each thread owns a 4 x 4 block of entries.
-constexpr int CK_T = 64, CK_KB = 32;
+// 64 x 64 sub-tiles of (row, column) entries; K consumed in blocks of 40
+// (K = 80 at D = 64 in two) decoded to float in LDS; each thread owns a
+// 4 x 4 block of entries (rows 4 ty + u, columns 4 tx + v).  The reduction
+// scratch reuses the operand tiles' LDS.
+constexpr int CK_T = 64, CK_KB = 40, CKM = 2048, CK_SUB = CKM / CK_T;
 
-__global__ void __launch_bounds__(256) k_check64(int prec, int units, int K, const void* A, const void* B, int64_t n,
-                                                 int64_t m, const float* la2, const float* lb2, double* rsum,
-                                                 double* kl) {
-    __shared__ float As[CK_T][CK_KB + 1];
-    __shared__ float Bs[CK_T][CK_KB + 1];
+int check_tiles(int64_t len) { return (int)((len + CKM - 1) / CKM); }
+
+__global__ void __launch_bounds__(256) k_check64_tiles(int prec, int units, int K, const void* A, const void* B,
+                                                       int64_t n, int64_t m, const float* la2, const float* lb2,
+                                                       double* rpart, double* klpart, double* cpart) {
+    constexpr int TILE_FLOATS = CK_T * (CK_KB + 1);
+    static_assert(2 * TILE_FLOATS * sizeof(float) >= 2 * 16 * CK_T * sizeof(double), "row scratch fits");
+    static_assert(TILE_FLOATS * sizeof(float) >= 16 * CK_T * sizeof(double), "column scratch fits");
+    __shared__ double tiles_mem[(2 * TILE_FLOATS + 1) / 2];
     __shared__ float lbs[CK_T];
-    __shared__ double red[2][16][CK_T];
+    __shared__ double colacc[CKM];
+    float(*As)[CK_KB + 1] = reinterpret_cast<float(*)[CK_KB + 1]>(tiles_mem);
+    float(*Bs)[CK_KB + 1] = reinterpret_cast<float(*)[CK_KB + 1]>(reinterpret_cast<float*>(tiles_mem) + TILE_FLOATS);
+    // reduction scratch over the operand tiles (used only between K loops)
+    double(*redc)[CK_T] = reinterpret_cast<double(*)[CK_T]>(tiles_mem);
+    double(*redr)[16][CK_T] = reinterpret_cast<double(*)[16][CK_T]>(tiles_mem);
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int64_t r0 = (int64_t)blockIdx.x * CK_T;
-    double rs[4] = {0, 0, 0, 0}, kr[4] = {0, 0, 0, 0};
-    double la[4];
+    const int rt = blockIdx.y, ct = blockIdx.x;
+    const int64_t R0 = (int64_t)rt * CKM, C0 = (int64_t)ct * CKM;
+    for (int j = tid; j < CKM; j += 256) colacc[j] = 0.0;
+    for (int rs = 0; rs < CK_SUB && R0 + rs * CK_T < n; ++rs) {
+        const int64_t r0 = R0 + rs * CK_T;
+        double rsum[4] = {0, 0, 0, 0}, rkl[4] = {0, 0, 0, 0}, la[4];
+        bool rin[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t i = r0 + ty * 4 + u;
-        la[u] = (i < n && kl) ? (double)la2[i] : 0.0;
-    }
-    for (int64_t c0 = 0; c0 < m; c0 += CK_T) {
-        double acc[4][4];
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = r0 + ty * 4 + u;
+            rin[u] = i < n;
+            la[u] = rin[u] ? (double)la2[i] : 0.0;
+        }
+        for (int cs = 0; cs < CK_SUB && C0 + cs * CK_T < m; ++cs) {
+            const int64_t c0 = C0 + cs * CK_T;
+            double acc[4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-        for (int k0 = 0; k0 < K; k0 += CK_KB) {
-            __syncthreads();
-            for (int e = tid; e < CK_T * CK_KB; e += 256) {
-                const int rr = e / CK_KB, kk = e - rr * CK_KB;
-                const int64_t i = r0 + rr, j = c0 + rr;
-                const int k = k0 + kk;
-                As[rr][kk] = (i < n && k < K) ? pack_elem(A, prec, units, (int)i, k) : 0.f;
-                Bs[rr][kk] = (j < m && k < K) ? pack_elem(B, prec, units, (int)j, k) : 0.f;
-            }
-            if (tid < CK_T) lbs[tid] = (lb2 && c0 + tid < m) ? lb2[c0 + tid] : 0.f;
-            __syncthreads();
+                for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            for (int k0 = 0; k0 < K; k0 += CK_KB) {
+                __syncthreads();
+                for (int e = tid; e < CK_T * CK_KB; e += 256) {
+                    const int rr = e / CK_KB, kk = e - rr * CK_KB;
+                    const int64_t i = r0 + rr, j = c0 + rr;
+                    const int k = k0 + kk;
+                    As[rr][kk] = (i < n && k < K) ? pack_elem(A, prec, units, (int)i, k) : 0.f;
+                    Bs[rr][kk] = (j < m && k < K) ? pack_elem(B, prec, units, (int)j, k) : 0.f;
+                }
+                if (tid < CK_T) lbs[tid] = c0 + tid < m ? lb2[c0 + tid] : 0.f;
+                __syncthreads();
 #pragma unroll 4
-            for (int kk = 0; kk < CK_KB; ++kk) {
-                double av[4], bv[4];
+                for (int kk = 0; kk < CK_KB; ++kk) {
+                    double av[4], bv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = (double)As[ty * 4 + u][kk];
+                        bv[u] = (double)Bs[tx * 4 + u][kk];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+                }
+            }
+            double csum[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (c0 + tx * 4 + v >= m) continue;
+                const double lbj = (double)lbs[tx * 4 + v];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    av[u] = (double)As[ty * 4 + u][kk];
-                    bv[u] = (double)Bs[tx * 4 + u][kk];
+                    if (!rin[u]) continue;
+                    const double pv = exp2(acc[u][v]);
+                    rsum[u] += pv;
+                    if (pv > 0.0) rkl[u] += pv * (acc[u][v] - la[u] - lbj);
+                    csum[v] += pv;
                 }
+            }
+            // column sums of the sub-tile over its 16 row groups, fixed order
+            __syncthreads();  // every thread is done reading the operand tiles
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+            for (int v = 0; v < 4; ++v) redc[ty][tx * 4 + v] = csum[v];
+            __syncthreads();
+            if (tid < CK_T) {
+                double q = 0.0;
+                for (int t = 0; t < 16; ++t) q += redc[t][tid];
+                colacc[cs * CK_T + tid] += q;
             }
         }
+        // row sums of the macro tile's columns over the 16 column groups
+        __syncthreads();
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t j = c0 + tx * 4 + v;
-            if (j >= m) continue;
-            const double lbj = (double)lbs[tx * 4 + v];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double p = exp2(acc[u][v]);
-                rs[u] += p;
-                if (kl && p > 0.0) kr[u] += p * (acc[u][v] - la[u] - lbj);
-            }
+        for (int u = 0; u < 4; ++u) {
+            redr[0][tx][ty * 4 + u] = rsum[u];
+            redr[1][tx][ty * 4 + u] = rkl[u];
         }
-    }
-    // reduce over the 16 threads sharing rows, fixed order
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        red[0][tx][ty * 4 + u] = rs[u];
-        red[1][tx][ty * 4 + u] = kr[u];
+        __syncthreads();
+        if (tid < CK_T && r0 + tid < n) {
+            double q = 0.0, w = 0.0;
+            for (int t = 0; t < 16; ++t) {
+                q += redr[0][t][tid];
+                w += redr[1][t][tid];
+            }
+            rpart[(size_t)ct * n + r0 + tid] = q;
+            klpart[(size_t)ct * n + r0 + tid] = w;
+        }
     }
     __syncthreads();
-    if (tid < CK_T) {
-        const int64_t i = r0 + tid;
-        double s = 0.0, q = 0.0;
-        for (int t = 0; t < 16; ++t) {
-            s += red[0][t][tid];
-            q += red[1][t][tid];
+    for (int j = tid; j < CKM && C0 + j < m; j += 256) cpart[(size_t)rt * m + C0 + j] = colacc[j];
+}
+
+// r64_i = sum over column tiles of the row partials (and kl), c64_j over row
+// tiles, in tile order.
+__global__ void __launch_bounds__(256) k_check64_reduce(const double* rpart, const double* klpart, const double* cpart,
+                                                        int n_ct, int n_rt, int64_t n, int64_t m, double* r64,
+                                                        double* kl, double* c64) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        double q = 0.0, w = 0.0;
+        for (int c = 0; c < n_ct; ++c) {
+            q += rpart[(size_t)c * n + t];
+            w += klpart[(size_t)c * n + t];
         }
-        if (i < n) {
-            rsum[i] = s;
-            if (kl) kl[i] = q * 0.6931471805599453;
-        }
+        r64[t] = q;
+        kl[t] = w * 0.6931471805599453;
+    } else if (t < n + m) {
+        const int64_t j = t - n;
+        double q = 0.0;
+        for (int r = 0; r < n_rt; ++r) q += cpart[(size_t)r * m + j];
+        c64[j] = q;
     }
 }
 
-hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols, int64_t n, int64_t n_pad, int64_t m,
-                          int64_t m_pad, const float* la2, const float* lb2, double* rsum, double* kl,
+size_t check64_part_doubles(int64_t n, int64_t m) {
+    return 2 * (size_t)check_tiles(m) * n + (size_t)check_tiles(n) * m;
+}
+
+hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols, int64_t n, int64_t m,
+                          const float* la2, const float* lb2, double* part, double* r64, double* kl, double* c64,
                           hipStream_t stream) {
-    (void)n_pad;
-    (void)m_pad;
     const int K = pack_k(prec, d);
     const int units = pack_units(prec, d);
-    hipLaunchKernelGGL(k_check64, dim3((unsigned)((n + CK_T - 1) / CK_T)), dim3(256), 0, stream, prec, units, K,
-                       Arows, Bcols, n, m, la2, lb2, rsum, kl);
+    const int n_rt = check_tiles(n), n_ct = check_tiles(m);
+    double* rpart = part;
+    double* klpart = part + (size_t)n_ct * n;
+    double* cpart = part + 2 * (size_t)n_ct * n;
+    hipLaunchKernelGGL(k_check64_tiles, dim3((unsigned)n_ct, (unsigned)n_rt), dim3(256), 0, stream, prec, units, K,
+                       Arows, Bcols, n, m, la2, lb2, rpart, klpart, cpart);
+    hipLaunchKernelGGL(k_check64_reduce, dim3((unsigned)((n + m + 255) / 256)), dim3(256), 0, stream, rpart, klpart,
+                       cpart, n_ct, n_rt, n, m, r64, kl, c64);
     return hipGetLastError();
 }
 

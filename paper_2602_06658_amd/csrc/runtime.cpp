@@ -436,6 +436,7 @@ Status Solve::buffers(bool dry) {
     momx_ = getd("momx", 2 + D_ * D_ + D_);
     momy_ = getd("momy", 2 + E_ * E_ + E_);
     mompart_ = getd("mompart", std::max(gwk::moments_part_doubles(n_, D_), gwk::moments_part_doubles(m_, E_)));
+    chk_ = geo_.path == 0 ? getd("chk", gwk::check64_part_doubles(n_, m_)) : nullptr;
     return st;
 }
 
@@ -629,10 +630,8 @@ Status Solve::finish_enqueue(gw_result* out) {
         GW_HIP(gwk::launch_check64_direct(D_, Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_, U_[pa_], Ul_[pa_], kap, m_, n_,
                                           lb2_, nullptr, c64, nullptr, st_));
     } else {
-        GW_HIP(gwk::launch_check64(prec_, D_, packA_[pa_], packB_[pb_], n_, n_pad_, m_, m_pad_, la2_, lb2_, r64, kl64,
+        GW_HIP(gwk::launch_check64(prec_, D_, packA_[pa_], packB_[pb_], n_, m_, la2_, lb2_, chk_, r64, kl64, c64,
                                    st_));
-        GW_HIP(gwk::launch_check64(prec_, D_, packB_[pb_], packA_[pa_], m_, m_pad_, n_, n_pad_, lb2_, nullptr, c64,
-                                   nullptr, st_));
     }
     GW_HIP(gwk::launch_check_final(r64, kl64, n_, a_, c64, m_, b_, asum_, bsum_, scal_, st_));
     c_.prof.end(st_);

@@ -247,6 +247,7 @@ class Solve {
     double* scal_ = nullptr;
     int* ctl_ = nullptr;
     double *momx_ = nullptr, *momy_ = nullptr, *mompart_ = nullptr;
+    double* chk_ = nullptr;  // FP64 check partials (MFMA path)
     int cov_tw_ = 0;
 };
 
