@@ -132,6 +132,14 @@ gw_status gw_create(gw_ctx** out, int device, void* hip_stream,
 gw_status gw_set_penalty(gw_ctx* ctx, int side, int kind, double p,
                          int lifted_dim, int n_landmarks, uint64_t seed);
 
+/* The landmark subset the seeded choice gives (host only, no GPU work):
+   writes min(n_landmarks, n) sorted indices into idx_host (caller
+   allocated): the first entries of a Fisher-Yates shuffle of 0..n-1 driven
+   by SplitMix64 (Steele, Lea, Flood 2014) started at seed.  The source side
+   of a served request uses seed, the target side seed + 1.  Returns
+   GW_EINVAL for n < 1, n_landmarks < 1 or a null pointer. */
+gw_status gw_seeded_landmarks(int64_t n, int n_landmarks, uint64_t seed, int64_t* idx_host);
+
 /* Use explicit landmark indices (host array of n_landmarks distinct indices
    into the next solve's points of that side) instead of the seeded choice.
    For GW_PEN_POWER only; clears fitted landmarks of that side. */

@@ -6,7 +6,7 @@ The compute runs in ``libgwmi.so`` (hand-written HIP kernels behind the C ABI
 of ``include/gw.h``); this package only marshals arguments.
 """
 from . import _lib  # noqa: F401
-from ._lib import GWError, LIB_PATH, load  # noqa: F401
+from ._lib import GWError, LIB_PATH, load, seeded_landmarks  # noqa: F401
 
 
 def __getattr__(name):

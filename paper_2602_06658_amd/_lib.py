@@ -97,6 +97,8 @@ SIGNATURES = {
     "gw_set_penalty": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_uint64]),
     "gw_set_landmarks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "gw_seeded_landmarks": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "gw_lift": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                ctypes.c_void_p, ctypes.c_void_p]),
     "gw_feature_dim": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -170,3 +172,16 @@ class GWError(RuntimeError):
         self.code = code
         name = STATUS_NAMES[code] if 0 <= code < len(STATUS_NAMES) else str(code)
         super().__init__(f"{name}: {msg}")
+
+
+def seeded_landmarks(n: int, n_landmarks: int, seed: int):
+    """Landmark indices the library's seeded choice gives for n points
+    (gw_seeded_landmarks; host only): a sorted list of min(n_landmarks, n)
+    indices."""
+    lib = load()
+    k = min(int(n_landmarks), int(n))
+    out = (ctypes.c_int64 * max(k, 1))()
+    rc = lib.gw_seeded_landmarks(int(n), int(n_landmarks), ctypes.c_uint64(seed), out)
+    if rc != GW_OK:
+        raise GWError(rc, "gw_seeded_landmarks failed")
+    return [int(v) for v in out[:k]]

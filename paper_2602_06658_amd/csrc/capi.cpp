@@ -1,4 +1,5 @@
 // extern "C" entry points of libgwmi.so (declared in include/gw.h).
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -54,6 +55,13 @@ gw_status gw_set_penalty(gw_ctx* ctx, int side, int kind, double p, int lifted_d
         c.lm.fitted = false;
     }
     return ret(ctx, Status::ok());
+}
+
+gw_status gw_seeded_landmarks(int64_t n, int n_landmarks, uint64_t seed, int64_t* idx_host) {
+    if (n < 1 || n_landmarks < 1 || !idx_host) return GW_EINVAL;
+    const std::vector<int64_t> idx = gwr::seeded_landmarks(n, n_landmarks, seed);
+    std::copy(idx.begin(), idx.end(), idx_host);
+    return GW_OK;
 }
 
 gw_status gw_set_landmarks(gw_ctx* ctx, int side, const int64_t* idx_host, int n_landmarks) {

@@ -71,3 +71,35 @@ def test_struct_layouts_match_the_header():
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_splitmix64_reference_outputs():
+    """The seeded-input generator reproduces the published first outputs of
+    SplitMix64 from state 0."""
+    from workloads import splitmix64_stream
+
+    gen = splitmix64_stream(0)
+    assert [next(gen) for _ in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("n,nl,seed", [(1, 1, 3), (10, 4, 0), (1000, 256, 7000), (5000, 2048, 2 ** 63 + 5),
+                                       (300, 512, 11)])
+def test_seeded_landmarks_match_the_generator(n, nl, seed):
+    """gw_seeded_landmarks (host code, no GPU) gives the subset that the
+    SplitMix64 Fisher-Yates generator of the seeded inputs gives."""
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libgwmi.so not built")
+    from workloads import splitmix64_landmarks
+
+    got = L.seeded_landmarks(n, nl, seed)
+    ref = splitmix64_landmarks(n, nl, seed)
+    assert got == ref.tolist()
+    assert len(got) == min(n, nl) and len(set(got)) == len(got) and got == sorted(got)
+    assert 0 <= got[0] and got[-1] < n
+
+
+def test_seeded_landmarks_rejects_bad_arguments():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libgwmi.so not built")
+    with pytest.raises(L.GWError):
+        L.seeded_landmarks(0, 4, 1)

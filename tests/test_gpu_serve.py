@@ -5,6 +5,10 @@ uneven requests on one GPU.
   gw_solve by itself and the same request served among others of different
   sizes give identical potentials, Gamma and loss (the batched launches run
   the same per-problem work; compared bit for bit).
+* Served results match the FP64 oracle on the same inputs: the features
+  come from the oracle's own landmark kernel PCA on the landmark subsets the
+  library's seeded choice gives (reproduced by the SplitMix64 generator of
+  the seeded inputs).
 * Admission respects the slot count and the HBM budget; a request larger
   than the budget is rejected; a queued request can be cancelled.
 """
@@ -12,7 +16,8 @@ import numpy as np
 import pytest
 import torch
 
-from workloads import config4_requests
+from oracle import gw_oracle as O
+from workloads import config4_requests, splitmix64_landmarks
 
 pytestmark = pytest.mark.gpu
 
@@ -98,3 +103,37 @@ def test_cancel_queued(gw):
     assert np.isfinite(srv.wait(tickets[1])["loss_lift"])
     assert srv.stats()["cancelled"] == 1
     srv.close()
+
+
+def f32(v):
+    return np.asarray(v, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-3)])
+def test_served_requests_match_oracle(gw, prec, tol):
+    """Eight requests shaped like the serving workload (sizes 300-1200 per
+    side, d = 2 or 3, |x - x'| lifted to D = 32 with 256 seeded landmarks per
+    side), served four at a time; each loss against the oracle's.  The
+    tolerances are the path's (FP32 1e-5, BF16 1e-3) widened for FP32 by the
+    eigensolver's difference in the lifted features (~1e-5)."""
+    reqs = [p for _, p in config4_requests(n_requests=8, lo=300, hi=1200, lifted_dim=D, seed_base=4300)]
+    eps, n_outer, n_inner, nl = 0.05, 5, 40, 256
+    weights = [(f32(p.a) / f32(p.a).sum(), f32(p.b) / f32(p.b).sum()) for p in reqs]
+    ctx = gw.Context()
+    srv = gw.Server(ctx, max_slots=4)
+    tickets = [srv.submit(dev(p.x), dev(a), dev(p.y), dev(b), eps, eps, n_outer, n_inner, precision=prec,
+                          penalty="power", p=1.0, lifted_dim=D, n_landmarks=nl, seed=500 + 2 * k)
+               for k, (p, (a, b)) in enumerate(zip(reqs, weights))]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, (p, (a, b), out) in enumerate(zip(reqs, weights, outs)):
+        ix = splitmix64_landmarks(p.n, nl, 500 + 2 * k)
+        iy = splitmix64_landmarks(p.m, nl, 500 + 2 * k + 1)
+        X = O.landmark_features(f32(p.x), a, O.fit_landmarks(f32(p.x)[ix], 1.0, D))
+        Y = O.landmark_features(f32(p.y), b, O.fit_landmarks(f32(p.y)[iy], 1.0, D))
+        ref = O.cnt_gw(a, b, X, Y, eps, eps, n_outer, n_inner)
+        ref_loss = O.lifted_loss(X, Y, a, b, ref.pi)
+        rel = abs(out["loss_lift"] - ref_loss) / abs(ref_loss)
+        print(f"request {k} ({p.n}x{p.m}, d={p.x.shape[1]}) {prec}: loss {out['loss_lift']:.8g} "
+              f"oracle {ref_loss:.8g} rel {rel:.2e} err {out['marginal_err']:.2e}")
+        assert rel < tol

@@ -17,6 +17,8 @@ from .synth import (  # noqa: F401
     subsample,
     rotated_copy,
     landmark_indices,
+    splitmix64_landmarks,
+    splitmix64_stream,
     grad_points,
     scale_features,
     c5_subsample,

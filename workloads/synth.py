@@ -210,6 +210,36 @@ def landmark_indices(n: int, n_landmarks: int, seed: int) -> np.ndarray:
     return np.sort(perm[: min(n_landmarks, n)])
 
 
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64_stream(seed: int):
+    """SplitMix64 (Steele, Lea, Flood 2014): state += 0x9E3779B97F4A7C15,
+    output = the state through two xor-shift-multiply rounds and a final
+    xor-shift."""
+    state = seed & _MASK64
+    while True:
+        state = (state + 0x9E3779B97F4A7C15) & _MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        yield z ^ (z >> 31)
+
+
+def splitmix64_landmarks(n: int, n_landmarks: int, seed: int) -> np.ndarray:
+    """The seeded landmark choice for requests that carry a seed instead of
+    indices: a Fisher-Yates shuffle of 0..n-1 (i from n-1 down to 1 swaps
+    with j = next() mod (i + 1)), first n_landmarks entries, sorted.  A random
+    draw of the method, so both the library and the oracle's inputs use this
+    one published generator."""
+    perm = list(range(n))
+    gen = splitmix64_stream(seed)
+    for i in range(n - 1, 0, -1):
+        j = next(gen) % (i + 1)
+        perm[i], perm[j] = perm[j], perm[i]
+    return np.sort(np.array(perm[: min(n_landmarks, n)], dtype=np.int64))
+
+
 def subsample(prob: Problem, k_src: int, k_tgt: int, seed: int) -> Problem:
     """Seeded subsample of both clouds; weights renormalised to sum 1."""
     rng = np.random.default_rng(seed)
