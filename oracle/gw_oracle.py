@@ -25,6 +25,9 @@ Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
                                                     agreement, permutation
                                                     enumeration, rigid motion,
                                                     monotone objective, Thm 4.5
+    sgw_divergence                                - Thm 4.3: zero between isometric
+                                                    measures, non-negative; symmetric
+                                                    in its two arguments
     landmark_lift, kernel_from_cost, kernel_pca   - full-rank exact embedding
     grad_positions, grad_weights                  - quartic-form envelope,
                                                     central finite differences,
@@ -499,6 +502,23 @@ def sinkhorn_converged(a, b, c, eps, f0=None, g0=None, tol=1e-14, max_iter=10000
             if stall >= 10 and err < 1e-12:
                 break
     return f, g
+
+
+def sgw_divergence(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, inner_tol=None) -> dict:
+    """Sinkhorn-GW divergence (Section 4, "Entropic Bias"): the EGW value of
+    the pair minus half the EGW values of each measure with itself,
+        SGW = GW_eps(alpha, beta) - (GW_eps(alpha, alpha) + GW_eps(beta, beta)) / 2,
+    each GW_eps the EGW objective L(pi) + eps KL(pi | a x b) of Algorithm 1
+    run from Gamma_0 = 0 with the same schedule (eps the last temperature;
+    inner_tol as in cnt_gw)."""
+    def one(p, P, q, Q):
+        res = cnt_gw(p, q, P, Q, eps_start, eps_end, n_outer, n_inner, inner_tol=inner_tol)
+        return egw_objective(P, Q, p, q, res.pi, res.eps)
+
+    xy = one(a, X, b, Y)
+    xx = one(a, X, a, X)
+    yy = one(b, Y, b, Y)
+    return {"sgw": xy - 0.5 * (xx + yy), "gw_xy": xy, "gw_xx": xx, "gw_yy": yy}
 
 
 def cnt_gw_converged(a, b, X, Y, eps, gamma0=None, tol=1e-13, max_outer=5000,
