@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three plain 256 MiB device copies first, as the scale for HBM byte counters")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--sgw-only", action="store_true",
+                    help="measure only the Sinkhorn-GW divergence (three solves) on the 20k workload")
+    ap.add_argument("--sgw-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving workload and print its measurements (for profiling it)")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -184,6 +187,36 @@ def serve_bench(args, gwm, torch, dev) -> dict:
     return out
 
 
+def sgw_bench(args, gwm, torch, dev) -> dict:
+    """Sinkhorn-GW divergence on the 20,000-point workload (3-D mixture,
+    target a noisy rigid motion, |x - x'| lifted to D = 32 with 2048
+    landmarks, eps 0.1 -> 0.005 over 30 x 100): three solves (x, y), (x, x),
+    (y, y) on the lifted features."""
+    from workloads import config2_fp32, landmark_indices
+
+    prob = config2_fp32()
+    t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
+    x, a, y, b = t(prob.x), t(prob.a), t(prob.y), t(prob.b)
+    ctx = gwm.Context()
+    for side, (npts, seed) in enumerate(((prob.n, 2101), (prob.m, 2102))):
+        ctx.set_penalty(side, "power", p=prob.p, lifted_dim=prob.lifted_dim, n_landmarks=2048)
+        ctx.set_landmarks(side, landmark_indices(npts, 2048, seed))
+    run = lambda: ctx.sgw(x, a, y, b, prob.eps_start, prob.eps_end, prob.n_outer, prob.n_inner,  # noqa: E731
+                          precision=args.sgw_precision)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = prob.n_outer * prob.n_inner
+    entries = float(prob.n * prob.m + prob.n * prob.n + prob.m * prob.m) * iters
+    return {"workload": f"gmm3d N=M={prob.n}, |x-x'| lifted to D={prob.lifted_dim} (2048 landmarks), "
+                        f"eps {prob.eps_start}->{prob.eps_end}, {prob.n_outer}x{prob.n_inner}, {args.sgw_precision}",
+            "seconds": dt, "entries_per_s": entries / dt, "sgw": res["sgw"], "gw_xy": res["gw_xy"],
+            "gw_xx": res["gw_xx"], "gw_yy": res["gw_yy"], "marginal_err": res["marginal_err"]}
+
+
 def cpu_baseline(prob, n_sample: int, iters: int) -> dict:
     """The FP64 oracle (as it stands) on a seeded subsample of the same
     workload: one outer step of `iters` symmetric Sinkhorn iterations plus the
@@ -220,6 +253,9 @@ def main():
     from workloads import config3_scale, landmark_indices
 
     dev = torch.device("cuda:0")
+    if args.sgw_only:
+        print(json.dumps({"sgw": sgw_bench(args, gwm, torch, dev)}), flush=True)
+        return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(args, gwm, torch, dev)}), flush=True)
         return

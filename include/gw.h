@@ -167,6 +167,28 @@ gw_status gw_solve(gw_ctx* ctx,
                    const gw_params* params, const float* gamma0,
                    gw_result* out);
 
+/* Result of gw_sgw. */
+typedef struct {
+    double sgw;                /* GW_eps(a, b) - (GW_eps(a, a) + GW_eps(b, b)) / 2 */
+    double gw_xy;              /* EGW objective of each of the three solves */
+    double gw_xx;
+    double gw_yy;
+    double marginal_err;       /* largest FP64 marginal error of the three */
+    int32_t dim_x, dim_y;      /* lifted dimensions D, E */
+} gw_sgw_result;
+
+/* Sinkhorn-GW divergence (Section 4, "Entropic Bias"; zero between
+   isometric measures and non-negative for CNT costs, Theorem 4.3): both
+   sides are lifted once with their penalties, then Algorithm 1 runs three
+   times on the lifted features, (x, y), (x, x) and (y, y), from Gamma_0 = 0
+   with the same params; each GW_eps is the EGW objective at the schedule's
+   last eps.  Same inputs and errors as gw_solve; params->use_init_potentials
+   is rejected (GW_EINVAL). */
+gw_status gw_sgw(gw_ctx* ctx,
+                 const float* x, int64_t n, int dx, const float* a,
+                 const float* y, int64_t m, int dy, const float* b,
+                 const gw_params* params, gw_sgw_result* out);
+
 /* Solve, then the envelope gradient of GW_eps (Appendix B.6, "EGW Gradient
    Computations"; Algorithm 12 through the frozen Nystrom map of Algorithm 13
    for GW_PEN_POWER) with respect to the positions and weights.  Any grad_*

@@ -56,6 +56,18 @@ class GwResult(ctypes.Structure):
     ]
 
 
+class GwSgwResult(ctypes.Structure):
+    _fields_ = [
+        ("sgw", ctypes.c_double),
+        ("gw_xy", ctypes.c_double),
+        ("gw_xx", ctypes.c_double),
+        ("gw_yy", ctypes.c_double),
+        ("marginal_err", ctypes.c_double),
+        ("dim_x", ctypes.c_int32),
+        ("dim_y", ctypes.c_int32),
+    ]
+
+
 class GwRequest(ctypes.Structure):
     _fields_ = [
         ("x", ctypes.c_void_p), ("n", ctypes.c_int64), ("dx", ctypes.c_int32), ("a", ctypes.c_void_p),
@@ -105,6 +117,9 @@ SIGNATURES = {
     "gw_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.POINTER(GwParams), ctypes.c_void_p, ctypes.POINTER(GwResult)]),
+    "gw_sgw": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.POINTER(GwParams), ctypes.POINTER(GwSgwResult)]),
     "gw_loss_and_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.POINTER(GwParams), ctypes.c_void_p,

@@ -142,6 +142,19 @@ class Context:
                                       ctypes.byref(prm), _ptr(g0t), ctypes.byref(r)))
         return _result_dict(r, f, g, gamma)
 
+    def sgw(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
+            precision="fp32", mode="auto") -> dict:
+        """Sinkhorn-GW divergence GW(x, y) - (GW(x, x) + GW(y, y)) / 2
+        (gw_sgw): three solves on the lifted features."""
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode, False, 0.0)
+        r = L.GwSgwResult()
+        self._check(self.lib.gw_sgw(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
+                                    ctypes.byref(prm), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in L.GwSgwResult._fields_}
+
     def loss_and_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                       precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, want=("x", "a", "y", "b")):
         x, a, y, b = self._prep(x, a, y, b)

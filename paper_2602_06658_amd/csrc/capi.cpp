@@ -146,6 +146,67 @@ gw_status gw_loss_and_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const
     return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, grad_x, grad_a, grad_y, grad_b, true);
 }
 
+// The context's penalties replaced by "features" for the solves of gw_sgw,
+// which run on features lifted beforehand; restored on every exit path.
+// (SideCfg holds plain handles, so moving it out and back leaves the fitted
+// landmarks untouched.)
+struct FeatureSides {
+    gwr::Ctx& c;
+    gwr::SideCfg saved[2];
+    explicit FeatureSides(gwr::Ctx& ctx) : c(ctx) {
+        for (int s = 0; s < 2; ++s) {
+            saved[s] = std::move(c.side[s]);
+            c.side[s] = gwr::SideCfg{};
+            c.side[s].kind = GW_PEN_FEATURES;
+        }
+    }
+    ~FeatureSides() {
+        for (int s = 0; s < 2; ++s) c.side[s] = std::move(saved[s]);
+    }
+};
+
+gw_status gw_sgw(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
+                 const float* b, const gw_params* params, gw_sgw_result* out) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (!out) return ret(ctx, gwr::fail(GW_EINVAL, "result is NULL"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = gwr::validate_inputs(ctx->c, x, n, dx, a, y, m, dy, b, params, "sgw.");
+    if (!st.good()) return ret(ctx, st);
+    if (params->use_init_potentials) return ret(ctx, gwr::fail(GW_EINVAL, "the divergence starts from zero potentials"));
+    gwr::Ctx& c = ctx->c;
+    const int D = gwr::feature_dim(c.side[0], dx), E = gwr::feature_dim(c.side[1], dy);
+    const int64_t n_pad = (n + 31) / 32 * 32, m_pad = (m + 31) / 32 * 32;
+    float* X = c.ws.get_t<float>("sgw.X", (size_t)n_pad * D, &st);
+    float* Y = c.ws.get_t<float>("sgw.Y", (size_t)m_pad * E, &st);
+    if (!st.good()) return ret(ctx, st);
+    st = gwr::lift_side(c, 0, x, n, dx, a, X, n_pad, "sgw.");
+    if (st.good()) st = gwr::lift_side(c, 1, y, m, dy, b, Y, m_pad, "sgw.");
+    if (!st.good()) return ret(ctx, st);
+    FeatureSides guard(c);
+    auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
+                   const float* wq, gw_result& r) -> Status {
+        gwr::Solve solve(c, "s.");
+        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, GW_PEN_FEATURES,
+                           GW_PEN_FEATURES, c.stream));
+        while (!solve.done()) GW_TRY(solve.outer_step());
+        return solve.finish(&r);
+    };
+    gw_result rxy{}, rxx{}, ryy{};
+    st = run(X, n, D, a, Y, m, E, b, rxy);
+    if (st.good()) st = run(X, n, D, a, X, n, D, a, rxx);
+    if (st.good()) st = run(Y, m, E, b, Y, m, E, b, ryy);
+    if (!st.good()) return ret(ctx, st);
+    out->gw_xy = rxy.egw_objective;
+    out->gw_xx = rxx.egw_objective;
+    out->gw_yy = ryy.egw_objective;
+    out->sgw = rxy.egw_objective - 0.5 * (rxx.egw_objective + ryy.egw_objective);
+    out->marginal_err = std::max(rxy.marginal_err, std::max(rxx.marginal_err, ryy.marginal_err));
+    out->dim_x = D;
+    out->dim_y = E;
+    return ret(ctx, Status::ok());
+}
+
 gw_status gw_set_profiling(gw_ctx* ctx, int enable) {
     if (!ctx) return GW_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->c.mu);

@@ -46,6 +46,7 @@ STRUCTS = {
     "gw_request": L.GwRequest,
     "gw_server_stats": L.GwServerStats,
     "gw_profile": L.GwProfile,
+    "gw_sgw_result": L.GwSgwResult,
 }
 
 

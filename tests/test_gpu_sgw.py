@@ -1,0 +1,92 @@
+"""Sinkhorn-GW divergence on the GPU (gw_sgw through the C ABI) against
+the FP64 oracle's three Algorithm 1 runs, and Theorem 4.3's isometry case.
+
+Tolerances: each EGW value and the divergence within 1e-5 of the pair's
+EGW value for FP32 (the loss tolerance of the FP32 path), 1e-3 for BF16;
+between isometric measures the GPU divergence is zero up to that FP32
+tolerance (the oracle's is zero to 1e-14)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gw_oracle as O
+from workloads import haar_rotation, landmark_indices, scale_features
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(v):
+    return torch.tensor(np.asarray(v, dtype=np.float32), device="cuda")
+
+
+def f32(v):
+    return np.asarray(v, dtype=np.float32).astype(np.float64)
+
+
+def _measure(seed, n, d):
+    rng = np.random.default_rng(seed)
+    x = f32(rng.standard_normal((n, d)) * np.array([1.0, 0.6, 0.3][:d]))
+    a = f32(rng.dirichlet(np.ones(n) * 3))
+    return rng, x, a / a.sum()
+
+
+def _compare(res, ref, tol):
+    scale = abs(ref["gw_xy"])
+    print({k: (res[k], ref[k]) for k in ("sgw", "gw_xy", "gw_xx", "gw_yy")}, "err", res["marginal_err"])
+    for k in ("gw_xy", "gw_xx", "gw_yy"):
+        assert abs(res[k] - ref[k]) <= tol * abs(ref[k]), k
+    assert abs(res["sgw"] - ref["sgw"]) <= tol * scale
+
+
+@pytest.mark.parametrize("eps", [0.5, 2.0])
+def test_sgw_sqeuclid_matches_oracle(gw, eps):
+    _, x, a = _measure(41, 300, 2)
+    _, y, b = _measure(42, 260, 3)
+    ctx = gw.Context()
+    res = ctx.sgw(dev(x), dev(a), dev(y), dev(b), eps, eps, 6, 80)
+    ref = O.sgw_divergence(a, b, O.centre(x, a), O.centre(y, b), eps, eps, 6, 80)
+    _compare(res, ref, 1e-5)
+    assert ref["sgw"] > 0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-3)])
+def test_sgw_features_mfma_path(gw, prec, tol):
+    """D = 32 features (the MFMA path) given as features."""
+    X = scale_features(43, 700, 32, decay=1.0) * 2.0
+    Y = scale_features(44, 650, 32, decay=1.0) * 2.0
+    a = np.full(700, 1.0 / 700)
+    b = np.full(650, 1.0 / 650)
+    X, Y = f32(O.centre(X, a)), f32(O.centre(Y, b))
+    ctx = gw.Context()
+    ctx.set_penalty(2, "features")
+    res = ctx.sgw(dev(X), dev(a), dev(Y), dev(b), 1.0, 1.0, 5, 60, precision=prec)
+    ref = O.sgw_divergence(a, b, O.centre(X, a), O.centre(Y, b), 1.0, 1.0, 5, 60)
+    _compare(res, ref, tol)
+
+
+def test_sgw_power_penalty_landmarks(gw):
+    """|x - x'| lifted to D = 16 with explicit landmarks per side."""
+    _, x, a = _measure(45, 500, 3)
+    _, y, b = _measure(46, 450, 2)
+    ix, iy = landmark_indices(500, 64, 1), landmark_indices(450, 64, 2)
+    ctx = gw.Context()
+    ctx.set_penalty(2, "power", p=1.0, lifted_dim=16, n_landmarks=64)
+    ctx.set_landmarks(0, ix)
+    ctx.set_landmarks(1, iy)
+    res = ctx.sgw(dev(x), dev(a), dev(y), dev(b), 0.5, 0.5, 5, 60)
+    X = O.landmark_features(x, a, O.fit_landmarks(x[ix], 1.0, 16))
+    Y = O.landmark_features(y, b, O.fit_landmarks(y[iy], 1.0, 16))
+    ref = O.sgw_divergence(a, b, X, Y, 0.5, 0.5, 5, 60)
+    _compare(res, ref, 1e-4)  # the eigensolver's difference in the features (~1e-5)
+
+
+def test_sgw_vanishes_between_isometric_measures(gw):
+    rng, x, a = _measure(47, 400, 3)
+    perm = rng.permutation(400)
+    y = f32((x @ haar_rotation(rng, 3).T + rng.uniform(-1, 1, 3))[perm])
+    b = a[perm]
+    ctx = gw.Context()
+    res = ctx.sgw(dev(x), dev(a), dev(y), dev(b), 0.2, 0.2, 6, 80)
+    print(res)
+    assert res["gw_xx"] > 1e-2
+    assert abs(res["sgw"]) <= 1e-5 * res["gw_xx"]
