@@ -257,7 +257,8 @@ class GWResult:
 
 
 def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
-           f0=None, g0=None, symmetric=True, record=False, inner_tol=None) -> GWResult:
+           f0=None, g0=None, symmetric=True, record=False, inner_tol=None,
+           anneal_final=False) -> GWResult:
     """Algorithm 1 (CNT-GW), Section 5, with a fixed number of outer steps.
 
     Per outer step t: Zbar_j = [Gamma_t Y_j, |Y_j|^2/2]; the squared-norm
@@ -265,7 +266,12 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     warm-started from the previous potentials (Appendix B.1, warm start);
     then X~_j = sum_i a_i X_i exp(8/eps (f_i + g_j - |Xbar_i - Zbar_j|^2)) and
     Gamma_{t+1} = sum_j b_j X~_j Y_j^T.  With inner_tol set, each inner solve
-    runs to that marginal error instead of n_inner iterations."""
+    runs to that marginal error instead of n_inner iterations.
+
+    anneal_final: Sinkhorn annealing in the last outer step only (Appendix
+    B.1, "Sinkhorn Annealing"): iteration n = 1..n_inner of that step runs
+    at eps_n = eps_T / sqrt(n); the plan, Gamma_T and the returned eps use
+    the last eps_n.  Potentials are in cost units, so nothing is rebased."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     X = np.asarray(X, np.float64)
@@ -277,15 +283,20 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     hist = []
     gamma_prev = gamma
     pi = None
-    eps_list = eps_schedule(eps_start, eps_end, n_outer)
-    for eps in eps_list:
+    eps_list = list(eps_schedule(eps_start, eps_end, n_outer))
+    for t, eps in enumerate(eps_list):
         zbar = np.concatenate([Y @ gamma.T, 0.5 * np.sum(Y * Y, axis=1, keepdims=True)], axis=1)
         cbar = sqdist(xbar, zbar)
-        epsp = eps / 8.0
-        if inner_tol is None:
-            f, g = sinkhorn(a, b, cbar, epsp, n_inner, f, g, symmetric)
+        if anneal_final and t == n_outer - 1:
+            for it in range(1, n_inner + 1):
+                f, g = sinkhorn(a, b, cbar, eps / np.sqrt(it) / 8.0, 1, f, g, symmetric)
+            eps = eps / np.sqrt(max(n_inner, 1))
+            eps_list[-1] = eps
+        elif inner_tol is None:
+            f, g = sinkhorn(a, b, cbar, eps / 8.0, n_inner, f, g, symmetric)
         else:
-            f, g = sinkhorn_converged(a, b, cbar, epsp, f, g, tol=inner_tol)
+            f, g = sinkhorn_converged(a, b, cbar, eps / 8.0, f, g, tol=inner_tol)
+        epsp = eps / 8.0
         expo = np.exp((f[:, None] + g[None, :] - cbar) / epsp)
         xt = expo.T @ (a[:, None] * X)          # X~_j = sum_i a_i X_i expo_ij
         new_gamma = (b[:, None] * xt).T @ Y
