@@ -95,6 +95,13 @@ typedef struct {
     double tol_gamma;          /* > 0: stop when |Gamma_t - Gamma_{t+1}|_F <= tol
                                   (Algorithm 1's loop condition; one 8-byte
                                   readback per outer step) */
+    int32_t anneal_final;      /* 1: Sinkhorn annealing in the scheduled last
+                                  outer step (Appendix B.1): its iteration
+                                  n = 1..n_inner runs at eps_T / sqrt(n), and
+                                  the plan, Gamma_T and the reported eps use the
+                                  last of them; 0: off.  Not applied when
+                                  tol_gamma stops the loop earlier. */
+    int32_t reserved;          /* must be 0 */
 } gw_params;
 
 typedef struct {

@@ -33,6 +33,8 @@ class GwParams(ctypes.Structure):
         ("mode", ctypes.c_int32),
         ("use_init_potentials", ctypes.c_int32),
         ("tol_gamma", ctypes.c_double),
+        ("anneal_final", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -183,6 +183,8 @@ static Status check_params(const gw_params* prm) {
     if (prm->mode < 0 || prm->mode > 2) return fail(GW_EINVAL, "unknown mode");
     if (prm->symmetric != 0 && prm->symmetric != 1) return fail(GW_EINVAL, "symmetric must be 0 or 1");
     if (!(prm->tol_gamma >= 0.0)) return fail(GW_EINVAL, "tol_gamma must be >= 0");
+    if (prm->anneal_final != 0 && prm->anneal_final != 1) return fail(GW_EINVAL, "anneal_final must be 0 or 1");
+    if (prm->reserved != 0) return fail(GW_EINVAL, "reserved must be 0");
     return Status::ok();
 }
 
@@ -563,18 +565,33 @@ Status Solve::outer_step() {
     if (done_) return Status::ok();
     GW_TRY(begin_outer());
     // Sinkhorn at eps_t / 8 (Algorithm 3 or 2), warm-started
-    for (int k = 0; k < prm_.n_inner; ++k) GW_TRY(inner_iteration(k));
+    for (int k = 0; k < prm_.n_inner; ++k) {
+        GW_TRY(before_inner(k));
+        GW_TRY(inner_iteration(k));
+    }
     return end_outer();
 }
 
-Status Solve::begin_outer() {
-    const int t = t_;
-    eps_t_ = eps_sched_[t];
+Status Solve::before_inner(int k) {
+    // Sinkhorn annealing in the scheduled last outer step (Appendix B.1):
+    // iteration n = k + 1 runs at eps_T / sqrt(n); the column operand and the
+    // potentials are re-expressed at the new temperature with the same Gamma
+    if (!prm_.anneal_final || t_ != prm_.n_outer - 1 || k == 0) return Status::ok();
+    eps_t_ = eps_sched_[t_] / std::sqrt((double)(k + 1));
     kappa_ = LOG2E * 8.0 / eps_t_;
-    // prologue (Algorithm 1: Zbar_j = [Gamma_t Y_j, |Y_j|^2 / 2]); potentials
-    // rebased to the new temperature and Gamma in FP64
+    return prologue(0);
+}
+
+Status Solve::begin_outer() {
+    eps_t_ = eps_sched_[t_];
+    kappa_ = LOG2E * 8.0 / eps_t_;
+    return prologue(t_ == 0 ? 1 : 0);
+}
+
+Status Solve::prologue(int first) {
+    // Algorithm 1: Zbar_j = [Gamma_t Y_j, |Y_j|^2 / 2]; potentials rebased
+    // from kappa_old_ to kappa_ and to Gamma in FP64
     const int expanded = geo_.path == 0 ? 1 : 0;
-    const int first = t == 0 ? 1 : 0;
     c_.prof.begin(GW_PROF_PROLOGUE, st_);
     GW_HIP(gwk::launch_prologue_cols(Y_, m_, m_pad_, E_, D_, gam_[gcur_], ym_, lb2_, have_init_ ? g_ : nullptr, first,
                                      expanded, kappa_, kappa_old_, Zs_, beta_, V_[pb_], Vl_[pb_], ms_, st_));

@@ -172,6 +172,9 @@ class Solve {
     // Stepwise control (serving loop): outer_step() is begin_outer(),
     // n_inner inner_iteration() calls, end_outer().
     Status begin_outer();
+    // Before inner iteration k of the current outer step (the annealing of
+    // the last step re-tempers the operands here); then inner_iteration(k).
+    Status before_inner(int k);
     Status inner_iteration(int k);
     Status end_outer();
     // Symmetric MFMA-path solves can run their Sinkhorn iterations in the
@@ -193,6 +196,7 @@ class Solve {
     double entries_per_outer() const { return (double)n_ * (double)m_ * prm_.n_inner; }
 
    private:
+    Status prologue(int first);
     Status configure(int64_t n, int dx, int64_t m, int dy, const gw_params& prm);
     Status buffers(bool dry = false);
     void make_half(int do_rows, int do_cols, float step, gwk::Operands& op, gwk::CombineArgs& ca);

@@ -232,6 +232,7 @@ gwr::Status round(gw_server* s, std::vector<Request*>& finished) {
             q->in_outer = true;
             q->k = 0;
         }
+        GW_TRY(q->solve->before_inner(q->k));
         if (q->solve->batchable()) {
             gwk::PassItem it;
             gwk::CombineArgs ma, ra;
