@@ -260,6 +260,8 @@ typedef struct {
     int32_t n_landmarks;
     uint64_t seed;
     float* f; float* g; float* gamma;  /* device outputs, caller allocated */
+    const float* gamma0;       /* device, D x E row-major initial Gamma, or
+                                  NULL for Gamma_0 = 0 (read at setup) */
 } gw_request;
 
 typedef struct {

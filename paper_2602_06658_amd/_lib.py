@@ -81,6 +81,7 @@ class GwRequest(ctypes.Structure):
         ("n_landmarks", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("f", ctypes.c_void_p), ("g", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+        ("gamma0", ctypes.c_void_p),
     ]
 
 

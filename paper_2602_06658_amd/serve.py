@@ -24,7 +24,7 @@ class Server:
 
     def submit(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                precision="fp32", mode="auto", penalty="sqeuclid", p=1.0, lifted_dim=0, n_landmarks=0,
-               seed=0, anneal_final=False) -> int:
+               seed=0, anneal_final=False, gamma0=None) -> int:
         """Queue one solve; returns its ticket.  The tensors stay referenced
         until the result is collected.  Landmarks of the |x - x'|^p penalty
         use seed for the source and seed + 1 for the target."""
@@ -44,11 +44,17 @@ class Server:
                                anneal_final=anneal_final)
         r.penalty, r.p, r.lifted_dim, r.n_landmarks, r.seed = pen, float(p), int(lifted_dim), int(n_landmarks), seed
         r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
+        g0 = None
+        if gamma0 is not None:
+            g0 = _dev_f32(gamma0, "gamma0")
+            if tuple(g0.shape) != (D, E):
+                raise ValueError(f"gamma0 must be {D} x {E}")
+            r.gamma0 = g0.data_ptr()
         t = ctypes.c_uint64()
         rc = self.lib.gw_server_submit(self.h, ctypes.byref(r), ctypes.byref(t))
         if rc != L.GW_OK:
             raise L.GWError(rc, "gw_server_submit rejected the request")
-        self._keep[t.value] = (x, a, y, b, f, g, gamma)
+        self._keep[t.value] = (x, a, y, b, f, g, gamma, g0)
         return t.value
 
     def _collect(self, ticket, rc, res, lat):
@@ -57,7 +63,7 @@ class Server:
         keep = self._keep.pop(ticket, None)
         if rc != L.GW_OK:
             raise L.GWError(rc, f"request {ticket} did not complete")
-        _, _, _, _, f, g, gamma = keep
+        f, g, gamma = keep[4:7]
         out = _result_dict(res, f, g, gamma)
         out["latency_s"] = lat.value
         return out
