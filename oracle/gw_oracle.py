@@ -33,6 +33,17 @@ Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
                                                     central finite differences,
                                                     translation / rotation
                                                     invariants
+    coarsen, nearest_centroid                     - Lloyd step worked by hand,
+                                                    scikit-learn K-Means, one
+                                                    point per cluster, weight /
+                                                    mean conservation, ties
+    interpolate                                   - one coarse point (closed
+                                                    form), the paper's bilinear
+                                                    form via scipy logsumexp,
+                                                    Sinkhorn fixed point
+    msgw                                          - fixed point of Algorithm 1
+                                                    kept from coarse to fine,
+                                                    rotation invariance
 """
 from __future__ import annotations
 
@@ -553,3 +564,154 @@ def cnt_gw_converged(a, b, X, Y, eps, gamma0=None, tol=1e-13, max_outer=5000,
         if step <= tol:
             break
     return gamma, pi, f, g
+
+
+# --------------------------------------------------------------------------
+# Multiscale-GW (Appendix B, "Implementation of Multiscale-GW":
+# Algorithm 7 with Coarsen and Algorithm 8, Interpolate)
+# --------------------------------------------------------------------------
+
+# Cluster sums are taken in exact integer arithmetic: every term a_i X_id is
+# rounded once to a multiple of 2^-S, so the sums do not depend on the order
+# of the additions.  S is the largest exponent with max|X| 2^S <= 2^61 (a
+# cluster sum is at most sum(a) max|X|, which stays below 2^63); weights use
+# 2^-61.
+WEIGHT_SCALE_EXP = 61
+
+
+def coarsen_scale_exp(X32: np.ndarray) -> int:
+    """Exponent S of the fixed-point grid 2^-S of the cluster sums a_i X_id."""
+    mx = float(np.max(np.abs(X32))) if X32.size else 0.0
+    if mx == 0.0:
+        return WEIGHT_SCALE_EXP
+    _, e = np.frexp(mx)            # mx = m 2^e with 1/2 <= m < 1
+    return WEIGHT_SCALE_EXP - int(e)
+
+
+def nearest_centroid(X32: np.ndarray, C32: np.ndarray, block: int = 256) -> np.ndarray:
+    """Index of the nearest centroid of every row, ties to the lowest index.
+    The squared distance is accumulated in single precision over the
+    coordinates in their order, each subtraction, square and addition
+    rounded on its own: the assignment is an integer decided by floating
+    point, and this fixes the precision and the order in which it is
+    decided."""
+    n, k = X32.shape[0], C32.shape[0]
+    best = np.full(n, np.inf, dtype=np.float32)
+    arg = np.zeros(n, dtype=np.int64)
+    for j0 in range(0, k, block):
+        cj = C32[j0:j0 + block]
+        dist = np.zeros((n, cj.shape[0]), dtype=np.float32)
+        for d in range(X32.shape[1]):
+            t = X32[:, d][:, None] - cj[:, d][None, :]
+            dist = dist + t * t
+        jb = np.argmin(dist, axis=1)                  # first minimum in the block
+        db = dist[np.arange(n), jb]
+        upd = db < best                               # earlier blocks win ties
+        best[upd] = db[upd]
+        arg[upd] = j0 + jb[upd]
+    return arg
+
+
+def coarsen(X, a, init_idx, n_lloyd: int):
+    """Coarsen (Appendix B, Multiscale-GW): weighted K-Means of the rows of
+    X with k = len(init_idx) centroids started at the rows init_idx, run for
+    n_lloyd Lloyd iterations (assignment to the nearest centroid, then each
+    centroid moved to the a-weighted mean of its cluster; an empty cluster
+    keeps its centroid).  The coarse weights are the aggregated weights of
+    the clusters of the last assignment, the coarse points the centroids of
+    the last update, and empty clusters are dropped (index order kept).
+
+    X and a are taken as the single-precision values a device receives;
+    centroids are held in single precision between iterations.
+    Returns (Xc float32 kc x D, ac float32 kc, assign int64 n, kept int64 kc)."""
+    if n_lloyd < 1:
+        raise ValueError("n_lloyd >= 1")
+    X32 = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+    a32 = np.asarray(a, dtype=np.float32)
+    n, dim = X32.shape
+    idx = np.asarray(init_idx, dtype=np.int64)
+    k = len(idx)
+    S = coarsen_scale_exp(X32)
+    ax = np.rint(a32.astype(np.float64)[:, None] * X32.astype(np.float64) * 2.0 ** S).astype(np.int64)
+    aw = np.rint(a32.astype(np.float64) * 2.0 ** WEIGHT_SCALE_EXP).astype(np.int64)
+    C32 = X32[idx].copy()
+    assign = np.zeros(n, dtype=np.int64)
+    w = np.zeros(k, dtype=np.int64)
+    for _ in range(n_lloyd):
+        assign = nearest_centroid(X32, C32)
+        sums = np.zeros((k, dim), dtype=np.int64)
+        np.add.at(sums, assign, ax)
+        w = np.zeros(k, dtype=np.int64)
+        np.add.at(w, assign, aw)
+        nz = w > 0
+        mean = (sums[nz].astype(np.float64) * 2.0 ** -S) / (w[nz].astype(np.float64)[:, None]
+                                                            * 2.0 ** -WEIGHT_SCALE_EXP)
+        C32[nz] = mean.astype(np.float32)
+    kept = np.nonzero(w > 0)[0]
+    ac = (w[kept].astype(np.float64) * 2.0 ** -WEIGHT_SCALE_EXP).astype(np.float32)
+    return C32[kept].copy(), ac, assign, kept
+
+
+def target_lift(Y, gamma) -> np.ndarray:
+    """Zbar_j = [Gamma Y_j, |Y_j|^2 / 2] (Algorithm 1, lifted target)."""
+    Y = np.asarray(Y, np.float64)
+    return np.concatenate([Y @ np.asarray(gamma, np.float64).T, 0.5 * np.sum(Y * Y, axis=1, keepdims=True)],
+                          axis=1)
+
+
+def interpolate(h, P, Q, w, gamma, eps, side: int) -> np.ndarray:
+    """Interpolate (Algorithm 8): the potential of fine points from the
+    coarse potential h of the other side, one Sinkhorn operator against the
+    coarse measure with the coarse map Gamma, in the convention of
+    Algorithm 1 (squared distances between lifted features at eps/8).
+
+    side 0: P are fine source features (N x D), Q coarse target features
+            (Mc x E) with weights w and potential h = g^c; returns f (N).
+    side 1: P are fine target features (M x E), Q coarse source features
+            (Nc x D) with weights w and potential h = f^c; returns g (M)."""
+    if side == 0:
+        pbar, qbar = lift(np.asarray(P, np.float64)), target_lift(Q, gamma)
+    else:
+        pbar, qbar = target_lift(P, gamma), lift(np.asarray(Q, np.float64))
+    c = sqdist(pbar, qbar)
+    return softmin_rows(np.asarray(w, np.float64), np.asarray(h, np.float64), c, eps / 8.0)
+
+
+@dataclass
+class MsGWResult:
+    fine: GWResult
+    coarse: GWResult
+    Xc: np.ndarray           # centred coarse source features
+    ac: np.ndarray
+    Yc: np.ndarray
+    bc: np.ndarray
+    f0: np.ndarray           # interpolated potentials the fine solve starts from
+    g0: np.ndarray
+
+
+def msgw(a, b, X, Y, init_x, init_y, n_lloyd, coarse: dict, fine: dict, gamma0=None) -> MsGWResult:
+    """Multiscale-GW (Algorithm 7).  X, Y: features of the fine measures
+    (centred with a, b); init_x, init_y: the rows that start each K-Means
+    (k = ceil(rho N) of them); coarse, fine: keyword schedules of cnt_gw
+    (eps_start, eps_end, n_outer, n_inner, ...).
+
+    The coarse features are re-centred with their weights, as Algorithm 1
+    requires of its inputs.  The coarse solve starts from gamma0 (zero by
+    default); the potentials are interpolated with the coarse Gamma at the
+    fine solve's first temperature, which then starts from Gamma^c and the
+    interpolated (f, g)."""
+    a64 = np.asarray(a, np.float64)
+    b64 = np.asarray(b, np.float64)
+    X = centre(X, a64)
+    Y = centre(Y, b64)
+    Xc, ac, _, _ = coarsen(X, a, init_x, n_lloyd)
+    Yc, bc, _, _ = coarsen(Y, b, init_y, n_lloyd)
+    ac64, bc64 = ac.astype(np.float64), bc.astype(np.float64)
+    Xc = centre(Xc, ac64)
+    Yc = centre(Yc, bc64)
+    rc = cnt_gw(ac64, bc64, Xc, Yc, gamma0=gamma0, **coarse)
+    eps_f = float(fine["eps_start"])
+    f0 = interpolate(rc.g, X, Yc, bc64, rc.gamma, eps_f, side=0)
+    g0 = interpolate(rc.f, Y, Xc, ac64, rc.gamma, eps_f, side=1)
+    rf = cnt_gw(a64, b64, X, Y, gamma0=rc.gamma, f0=f0, g0=g0, **fine)
+    return MsGWResult(rf, rc, Xc, ac64, Yc, bc64, f0, g0)
