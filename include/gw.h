@@ -196,6 +196,79 @@ gw_status gw_sgw(gw_ctx* ctx,
                  const float* y, int64_t m, int dy, const float* b,
                  const gw_params* params, gw_sgw_result* out);
 
+/* ---- Multiscale-GW (Appendix B, "Implementation of Multiscale-GW") ---- */
+
+/* Coarsen of Multiscale-GW: weighted K-Means of the rows of X (n x D,
+   device, row-major; 1 <= D <= 256) with weights w (n, device, > 0, summing
+   to 1), k = number of clusters (1 <= k <= n) started at the rows
+   gw_seeded_landmarks(n, k, seed) gives, n_lloyd (1..10000) Lloyd
+   iterations.  Each iteration assigns every row to its nearest centroid
+   (squared distance summed over the coordinates in order in single
+   precision without fused multiply-add, ties to the lowest index), then
+   moves each centroid to the weighted mean of its cluster; the cluster sums
+   are exact integer sums of rint(w_i X_id 2^S), S the largest exponent with
+   max|X| 2^S <= 2^61, and of rint(w_i 2^61); the mean is one FP64 division
+   rounded to single precision; an empty cluster keeps its centroid.
+   Outputs (device, caller allocated): Xc (k x D) and wc (k) receive the
+   non-empty clusters of the last assignment in index order, their
+   centroids and aggregated weights; assign (n, nullable) the cluster index
+   (0..k-1) of every row; *kc (host) their count.  GW_EINVAL on sizes out of
+   range, null pointers, non-finite X or invalid weights. */
+gw_status gw_kmeans(gw_ctx* ctx, const float* X, int64_t n, int D, const float* w,
+                    int64_t k, int n_lloyd, uint64_t seed,
+                    float* Xc, float* wc, int32_t* assign, int64_t* kc);
+
+/* Interpolate (Algorithm 8), in the potentials' convention of Algorithm 1:
+   out_q = -eps' ln sum_r w_r exp((h_r - |Pbar_q - Qbar_r|^2) / eps'),
+   eps' = eps / 8, over lifted features.  side 0: P (nq x D) are source
+   features, Q (nr x E) target features, Pbar = [P, |P|^2/2],
+   Qbar = [Gamma Q, |Q|^2/2], h = g of the coarse target, out = f.  side 1:
+   P (nq x E) target features, Q (nr x D) source features,
+   Pbar = [Gamma P, |P|^2/2], Qbar = [Q, |Q|^2/2], h = f, out = g.  gamma is
+   D x E row-major; every array is device memory; w > 0.  GW_EINVAL on
+   sizes out of range (D, E in 1..256), null pointers or eps <= 0. */
+gw_status gw_interpolate(gw_ctx* ctx, int side, const float* h,
+                         const float* P, int64_t nq, const float* Q, int64_t nr,
+                         const float* w, const float* gamma, int D, int E,
+                         double eps, float* out);
+
+/* Options of gw_msgw. */
+typedef struct {
+    double rho;        /* coarsening ratio in (0, 1]: ceil(rho n) and ceil(rho m) clusters */
+    int32_t n_lloyd;   /* Lloyd iterations of each K-Means, >= 1 */
+    int32_t reserved;  /* must be 0 */
+    uint64_t seed;     /* K-Means starts: gw_seeded_landmarks with seed (source), seed + 1 (target) */
+} gw_msgw_opts;
+
+/* Coarse-scale figures of gw_msgw. */
+typedef struct {
+    int64_t n_coarse, m_coarse;     /* non-empty clusters per side */
+    double coarse_loss_lift;        /* gw_result fields of the coarse solve */
+    double coarse_egw_objective;
+    double coarse_marginal_err;
+    double ms_coarsen;              /* wall-clock milliseconds per phase (the */
+    double ms_coarse_solve;         /* stream is synchronised between phases) */
+    double ms_interpolate;
+    double ms_fine_solve;
+} gw_msgw_info;
+
+/* Multiscale-GW (Algorithm 7): both sides are lifted once with their
+   penalties (features X, Y, centred), coarsened with gw_kmeans' procedure,
+   the coarse features re-centred with their weights; Algorithm 1 runs on
+   the coarse measures with params `coarse` from gamma0 (NULL: 0); f and g
+   of the fine points are interpolated (gw_interpolate) from the coarse
+   potentials with the coarse Gamma at fine->eps_start; then Algorithm 1
+   runs on the fine features with params `fine`, starting from the coarse
+   Gamma and the interpolated potentials.  out (f, g, gamma and the scalars)
+   is the fine solve's result; info (nullable) the coarse figures.  Inputs
+   and errors as gw_solve; use_init_potentials must be 0 in both params. */
+gw_status gw_msgw(gw_ctx* ctx,
+                  const float* x, int64_t n, int dx, const float* a,
+                  const float* y, int64_t m, int dy, const float* b,
+                  const gw_params* coarse, const gw_params* fine,
+                  const gw_msgw_opts* opts, const float* gamma0,
+                  gw_result* out, gw_msgw_info* info);
+
 /* Solve, then the envelope gradient of GW_eps (Appendix B.6, "EGW Gradient
    Computations"; Algorithm 12 through the frozen Nystrom map of Algorithm 13
    for GW_PEN_POWER) with respect to the positions and weights.  Any grad_*

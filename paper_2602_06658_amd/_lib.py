@@ -70,6 +70,29 @@ class GwSgwResult(ctypes.Structure):
     ]
 
 
+class GwMsgwOpts(ctypes.Structure):
+    _fields_ = [
+        ("rho", ctypes.c_double),
+        ("n_lloyd", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class GwMsgwInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_coarse", ctypes.c_int64),
+        ("m_coarse", ctypes.c_int64),
+        ("coarse_loss_lift", ctypes.c_double),
+        ("coarse_egw_objective", ctypes.c_double),
+        ("coarse_marginal_err", ctypes.c_double),
+        ("ms_coarsen", ctypes.c_double),
+        ("ms_coarse_solve", ctypes.c_double),
+        ("ms_interpolate", ctypes.c_double),
+        ("ms_fine_solve", ctypes.c_double),
+    ]
+
+
 class GwRequest(ctypes.Structure):
     _fields_ = [
         ("x", ctypes.c_void_p), ("n", ctypes.c_int64), ("dx", ctypes.c_int32), ("a", ctypes.c_void_p),
@@ -123,6 +146,17 @@ SIGNATURES = {
     "gw_sgw": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                               ctypes.POINTER(GwParams), ctypes.POINTER(GwSgwResult)]),
+    "gw_kmeans": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "gw_interpolate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_void_p]),
+    "gw_msgw": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                               ctypes.POINTER(GwParams), ctypes.POINTER(GwParams), ctypes.POINTER(GwMsgwOpts),
+                               ctypes.c_void_p, ctypes.POINTER(GwResult), ctypes.POINTER(GwMsgwInfo)]),
     "gw_loss_and_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.POINTER(GwParams), ctypes.c_void_p,

@@ -158,6 +158,62 @@ class Context:
                                     ctypes.byref(prm), ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in L.GwSgwResult._fields_}
 
+    def kmeans(self, X, w, k: int, n_lloyd: int = 10, seed: int = 0) -> dict:
+        """Coarsen of Multiscale-GW (gw_kmeans): weighted K-Means of the rows
+        of X (n, D) with weights w (n,).  Returns the non-empty clusters
+        (Xc, wc) in index order, the cluster of every row and their count."""
+        X = _dev_f32(X, "X")
+        w = _dev_f32(w, "w")
+        n, D = X.shape
+        Xc = torch.empty((k, D), dtype=torch.float32, device=X.device)
+        wc = torch.empty(k, dtype=torch.float32, device=X.device)
+        assign = torch.empty(n, dtype=torch.int32, device=X.device)
+        kc = ctypes.c_int64()
+        self._check(self.lib.gw_kmeans(self.h, _ptr(X), n, D, _ptr(w), int(k), int(n_lloyd), ctypes.c_uint64(seed),
+                                       _ptr(Xc), _ptr(wc), _ptr(assign), ctypes.byref(kc)))
+        kc = int(kc.value)
+        return {"Xc": Xc[:kc], "wc": wc[:kc], "assign": assign, "kc": kc}
+
+    def interpolate(self, side: int, h, P, Q, w, gamma, eps: float) -> torch.Tensor:
+        """Algorithm 8 (gw_interpolate): side 0 gives f of the source points P
+        from the coarse target (Q, w, h = g); side 1 gives g of the target
+        points P from the coarse source (Q, w, h = f).  gamma: (D, E)."""
+        h, P, Q, w, gamma = (_dev_f32(t, nm) for t, nm in ((h, "h"), (P, "P"), (Q, "Q"), (w, "w"),
+                                                            (gamma, "gamma")))
+        D, E = gamma.shape
+        out = torch.empty(P.shape[0], dtype=torch.float32, device=P.device)
+        self._check(self.lib.gw_interpolate(self.h, int(side), _ptr(h), _ptr(P), P.shape[0], _ptr(Q), Q.shape[0],
+                                            _ptr(w), _ptr(gamma), D, E, float(eps), _ptr(out)))
+        return out
+
+    def msgw(self, x, a, y, b, coarse: dict, fine: dict, rho: float = 0.1, n_lloyd: int = 10, seed: int = 0,
+             gamma0=None) -> dict:
+        """Multiscale-GW (gw_msgw, Algorithm 7).  coarse / fine: keyword
+        arguments of make_params (eps_start, eps_end, n_outer, n_inner,
+        symmetric, precision, mode, ...).  Returns the fine result with the
+        coarse figures under "info"."""
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        D, E = self.feature_dim(0, dx), self.feature_dim(1, dy)
+        f = torch.empty(n, dtype=torch.float32, device=x.device)
+        g = torch.empty(m, dtype=torch.float32, device=x.device)
+        gamma = torch.empty((D, E), dtype=torch.float32, device=x.device)
+        pc = make_params(**coarse)
+        pf = make_params(**fine)
+        o = L.GwMsgwOpts()
+        o.rho, o.n_lloyd, o.reserved, o.seed = float(rho), int(n_lloyd), 0, int(seed)
+        g0t = None if gamma0 is None else _dev_f32(gamma0, "gamma0")
+        r = L.GwResult()
+        r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
+        info = L.GwMsgwInfo()
+        self._check(self.lib.gw_msgw(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b), ctypes.byref(pc),
+                                     ctypes.byref(pf), ctypes.byref(o), _ptr(g0t), ctypes.byref(r),
+                                     ctypes.byref(info)))
+        out = _result_dict(r, f, g, gamma)
+        out["info"] = {k: getattr(info, k) for k, _ in L.GwMsgwInfo._fields_}
+        return out
+
     def loss_and_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                       precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, want=("x", "a", "y", "b")):
         x, a, y, b = self._prep(x, a, y, b)

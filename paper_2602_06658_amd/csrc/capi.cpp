@@ -146,25 +146,6 @@ gw_status gw_loss_and_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const
     return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, grad_x, grad_a, grad_y, grad_b, true);
 }
 
-// The context's penalties replaced by "features" for the solves of gw_sgw,
-// which run on features lifted beforehand; restored on every exit path.
-// (SideCfg holds plain handles, so moving it out and back leaves the fitted
-// landmarks untouched.)
-struct FeatureSides {
-    gwr::Ctx& c;
-    gwr::SideCfg saved[2];
-    explicit FeatureSides(gwr::Ctx& ctx) : c(ctx) {
-        for (int s = 0; s < 2; ++s) {
-            saved[s] = std::move(c.side[s]);
-            c.side[s] = gwr::SideCfg{};
-            c.side[s].kind = GW_PEN_FEATURES;
-        }
-    }
-    ~FeatureSides() {
-        for (int s = 0; s < 2; ++s) c.side[s] = std::move(saved[s]);
-    }
-};
-
 gw_status gw_sgw(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
                  const float* b, const gw_params* params, gw_sgw_result* out) {
     if (!ctx) return GW_EINVAL;
@@ -183,7 +164,7 @@ gw_status gw_sgw(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a,
     st = gwr::lift_side(c, 0, x, n, dx, a, X, n_pad, "sgw.");
     if (st.good()) st = gwr::lift_side(c, 1, y, m, dy, b, Y, m_pad, "sgw.");
     if (!st.good()) return ret(ctx, st);
-    FeatureSides guard(c);
+    gwr::FeatureSides guard(c);
     auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
                    const float* wq, gw_result& r) -> Status {
         gwr::Solve solve(c, "s.");

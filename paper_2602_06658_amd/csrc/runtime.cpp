@@ -211,6 +211,12 @@ static Status device_check(Ctx& c, const float* x, int64_t nx, const float* w, i
     return Status::ok();
 }
 
+Status check_points(Ctx& c, const float* x, int64_t nx, const float* w, int64_t nw, const std::string& tag,
+                    const char* what) {
+    double wsum = 0.0;
+    return device_check(c, x, nx, w, nw, tag, &wsum, what);
+}
+
 Status validate_inputs(Ctx& c, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
                        const float* b, const gw_params* prm, const std::string& tag) {
     GW_TRY(check_params(prm));

@@ -141,6 +141,11 @@ int feature_dim(const SideCfg& s, int d);
 Status lift_side(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
                  const std::string& tag);
 
+// Device check of nx values of x (finite) and nw weights (finite, > 0,
+// summing to 1 within 1e-5); waits for the result.
+Status check_points(Ctx& c, const float* x, int64_t nx, const float* w, int64_t nw, const std::string& tag,
+                    const char* what);
+
 // Host-side validation of a problem; launches the device checks and waits.
 Status validate_inputs(Ctx& c, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
                        const float* b, const gw_params* prm, const std::string& tag);
@@ -270,4 +275,24 @@ Status lift_nystrom(Ctx& c, int side, const float* x, int64_t n, int d, const fl
 
 namespace gwr {
 std::vector<int64_t> seeded_landmarks(int64_t n, int nl, uint64_t seed);
+}  // namespace gwr
+
+namespace gwr {
+// The context's penalties replaced by "features" for solves that run on
+// features lifted beforehand; restored on every exit path.  (SideCfg holds
+// plain handles, so moving it out and back leaves fitted landmarks alone.)
+struct FeatureSides {
+    Ctx& c;
+    SideCfg saved[2];
+    explicit FeatureSides(Ctx& ctx) : c(ctx) {
+        for (int s = 0; s < 2; ++s) {
+            saved[s] = std::move(c.side[s]);
+            c.side[s] = SideCfg{};
+            c.side[s].kind = GW_PEN_FEATURES;
+        }
+    }
+    ~FeatureSides() {
+        for (int s = 0; s < 2; ++s) c.side[s] = std::move(saved[s]);
+    }
+};
 }  // namespace gwr
