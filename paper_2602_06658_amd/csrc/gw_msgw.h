@@ -23,13 +23,14 @@ hipError_t launch_km_iteration(const float* X, int64_t n, int ldx, int D, const 
 // Non-empty clusters in index order: Xc (dense, D columns), wc, kept, *kc.
 hipError_t launch_km_compact(const unsigned long long* wsum, const float* C, int k, int D, int ldc, float* Xc,
                              float* wc, int* kept, int* kc, hipStream_t stream);
-// out_i = [G V_i, |V_i|^2 / 2] (G: D x dv row-major) or [V_i, |V_i|^2 / 2]
-// when G is NULL; zero-padded to ldo.
+// out_i = G V_i (G: D x dv row-major) or V_i when G is NULL, zero-padded to
+// ldo; half_i = |V_i|^2 / 2.
 hipError_t launch_lift_bar(const float* V, int64_t n, int ldv, int dv, const float* G, int D, float* out, int ldo,
-                           hipStream_t stream);
-// out_q = -eps' ln sum_r w_r exp((h_r - |P_q - Q_r|^2) / eps') over the first
-// dl coordinates; hb: nr floats of scratch.
-hipError_t launch_interp(const float* P, int64_t nq, int ldp, const float* Q, int nr, int ldq, int dl, const float* w,
-                         const float* h, double eps_prime, float* hb, float* out, hipStream_t stream);
+                           float* half, hipStream_t stream);
+// out_q = -eps' ln sum_r w_r exp((h_r - |Pbar_q - Qbar_r|^2) / eps'), Pbar_q =
+// [P_q (dl coordinates), ph_q], Qbar_r = [Q_r, qh_r]; hb: nr floats of scratch.
+hipError_t launch_interp(const float* P, int64_t nq, int ldp, const float* Q, int nr, int ldq, int dl,
+                         const float* ph, const float* qh, const float* w, const float* h, double eps_prime, float* hb,
+                         float* out, hipStream_t stream);
 
 }  // namespace gwk

@@ -4,7 +4,8 @@
 //     compaction of the non-empty clusters.
 //   - Algorithm 8 (Interpolate): one Sinkhorn operator of fine points
 //     against a coarse measure, f_q = -eps' ln sum_r w_r exp((h_r - |P_q - Q_r|^2) / eps'),
-//     over lifted features P = [X, |X|^2/2] and Q = [Gamma Y, |Y|^2/2].
+//     over lifted features P = [X, |X|^2/2] and Q = [Gamma Y, |Y|^2/2] (the
+//     last coordinate passed apart, so that D = 64 fills one 64-wide chunk).
 //
 // Both scans are one thread per point against tiles of MS_TJ reference rows
 // staged in LDS (every lane reads the same LDS word: a broadcast), with the
@@ -19,7 +20,7 @@ namespace gwk {
 
 constexpr int MS_THREADS = 256;
 constexpr int MS_TJ = 16;
-constexpr int MS_MAXDP = 320;  // coordinates of an LDS row: up to 256 + 1 lifted, in chunks of 64
+constexpr int MS_MAXDP = 256;  // coordinates of an LDS row: up to 256, in chunks of 64
 
 // ---------------------------------------------------------------------------
 // K-Means assignment: assign[i] = argmin_j |X_i - C_j|^2, ties to the lowest
@@ -192,12 +193,12 @@ __global__ void __launch_bounds__(1024) k_km_compact(const unsigned long long* _
 }
 
 // ---------------------------------------------------------------------------
-// Lifted features for Algorithm 8: out_i = [G V_i (or V_i), |V_i|^2 / 2],
-// zero-padded to ldo.
+// Lifted features for Algorithm 8: out_i = G V_i (or V_i), zero-padded to
+// ldo, and half_i = |V_i|^2 / 2, the last lifted coordinate.
 // ---------------------------------------------------------------------------
 
 __global__ void k_lift_bar(const float* __restrict__ V, int64_t n, int ldv, int dv, const float* __restrict__ G,
-                           int D, float* out, int ldo) {
+                           int D, float* out, int ldo, float* half) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float* v = V + i * ldv;
@@ -214,8 +215,8 @@ __global__ void k_lift_bar(const float* __restrict__ V, int64_t n, int ldv, int 
     } else {
         for (int d = 0; d < dv; ++d) o[d] = v[d];
     }
-    o[dl] = 0.5f * nv;
-    for (int d = dl + 1; d < ldo; ++d) o[d] = 0.f;
+    for (int d = dl; d < ldo; ++d) o[d] = 0.f;
+    half[i] = 0.5f * nv;
 }
 
 // hb_r = log2 w_r + kappa h_r, kappa = log2(e) / eps'.
@@ -230,15 +231,18 @@ __global__ void k_interp_bias(const float* __restrict__ w, const float* __restri
 template <int CH>
 __global__ void __launch_bounds__(MS_THREADS) k_interp(const float* __restrict__ P, int64_t nq, int ldp,
                                                        const float* __restrict__ Q, int nr, int ldq, int dl,
+                                                       const float* __restrict__ ph, const float* __restrict__ qh,
                                                        const float* __restrict__ hb, float kappa, float scale_out,
                                                        float* __restrict__ out) {
     const int NCH = (dl + CH - 1) / CH;
     const int DP = CH * NCH;
     __shared__ float tile[MS_TJ * MS_MAXDP];
     __shared__ float htile[MS_TJ];
+    __shared__ float qtile[MS_TJ];
     const int64_t i = blockIdx.x * (int64_t)MS_THREADS + threadIdx.x;
     const bool live = i < nq;
     const float* pi = P + (live ? i : 0) * (int64_t)ldp;
+    const float phi = live ? ph[i] : 0.f;
     float r[CH];
     if (NCH == 1) {
 #pragma unroll
@@ -252,11 +256,17 @@ __global__ void __launch_bounds__(MS_THREADS) k_interp(const float* __restrict__
             const int jj = e / DP, d = e - jj * DP;
             tile[e] = (jj < nj && d < dl) ? Q[(int64_t)(j0 + jj) * ldq + d] : 0.f;
         }
-        if (threadIdx.x < MS_TJ) htile[threadIdx.x] = threadIdx.x < nj ? hb[j0 + threadIdx.x] : -INFINITY;
+        if (threadIdx.x < MS_TJ) {
+            htile[threadIdx.x] = threadIdx.x < nj ? hb[j0 + threadIdx.x] : -INFINITY;
+            qtile[threadIdx.x] = threadIdx.x < nj ? qh[j0 + threadIdx.x] : 0.f;
+        }
         __syncthreads();
         float dist[MS_TJ];
 #pragma unroll
-        for (int jj = 0; jj < MS_TJ; ++jj) dist[jj] = 0.f;
+        for (int jj = 0; jj < MS_TJ; ++jj) {
+            const float t = phi - qtile[jj];
+            dist[jj] = t * t;
+        }
 #pragma unroll 1
         for (int c = 0; c < NCH; ++c) {
             if (NCH > 1) {
@@ -326,7 +336,7 @@ hipError_t launch_km_gather(const float* X, int ldx, int D, const int64_t* idx, 
 hipError_t launch_km_iteration(const float* X, int64_t n, int ldx, int D, const float* w, float* C, int k, int ldc,
                                int S, int* assign, unsigned long long* sums, unsigned long long* wsum,
                                hipStream_t stream) {
-    if (D < 1 || D > MS_MAXDP - 64 || k < 1 || n < 1) return hipErrorInvalidValue;
+    if (D < 1 || D > MS_MAXDP || k < 1 || n < 1) return hipErrorInvalidValue;
     const int64_t zc = (int64_t)k * D + k;  // sums and wsum are one allocation
     hipLaunchKernelGGL(k_km_zero, dim3(blocks_for(zc, 256)), dim3(256), 0, stream, sums, zc);
     MS_DISPATCH(k_km_assign, D, blocks_for(n, MS_THREADS), stream, X, n, ldx, D, (const float*)C, k, ldc, assign);
@@ -344,20 +354,22 @@ hipError_t launch_km_compact(const unsigned long long* wsum, const float* C, int
 }
 
 hipError_t launch_lift_bar(const float* V, int64_t n, int ldv, int dv, const float* G, int D, float* out, int ldo,
-                           hipStream_t stream) {
-    hipLaunchKernelGGL(k_lift_bar, dim3(blocks_for(n, 256)), dim3(256), 0, stream, V, n, ldv, dv, G, D, out, ldo);
+                           float* half, hipStream_t stream) {
+    hipLaunchKernelGGL(k_lift_bar, dim3(blocks_for(n, 256)), dim3(256), 0, stream, V, n, ldv, dv, G, D, out, ldo,
+                       half);
     return hipGetLastError();
 }
 
-hipError_t launch_interp(const float* P, int64_t nq, int ldp, const float* Q, int nr, int ldq, int dl, const float* w,
-                         const float* h, double eps_prime, float* hb, float* out, hipStream_t stream) {
+hipError_t launch_interp(const float* P, int64_t nq, int ldp, const float* Q, int nr, int ldq, int dl,
+                         const float* ph, const float* qh, const float* w, const float* h, double eps_prime, float* hb,
+                         float* out, hipStream_t stream) {
     if (dl < 1 || dl > MS_MAXDP || nr < 1 || nq < 1) return hipErrorInvalidValue;
     const double kappa = 1.4426950408889634 / eps_prime;
     hipLaunchKernelGGL(k_interp_bias, dim3(blocks_for(nr, 256)), dim3(256), 0, stream, w, h, (int64_t)nr,
                        (float)kappa, hb);
     const float scale_out = (float)(-eps_prime * 0.6931471805599453);
-    MS_DISPATCH(k_interp, dl, blocks_for(nq, MS_THREADS), stream, P, nq, ldp, Q, nr, ldq, dl, (const float*)hb,
-                (float)kappa, scale_out, out);
+    MS_DISPATCH(k_interp, dl, blocks_for(nq, MS_THREADS), stream, P, nq, ldp, Q, nr, ldq, dl, ph, qh,
+                (const float*)hb, (float)kappa, scale_out, out);
     return hipGetLastError();
 }
 

@@ -63,20 +63,21 @@ static Status interpolate(Ctx& c, int side, const float* h, const float* P, int6
                           int64_t nr, int ldq, const float* w, const float* gamma, int D, int E, double eps,
                           float* out, const std::string& tag) {
     Status st;
-    const int dl = D + 1;
-    const int ld = (dl + 3) / 4 * 4;
+    const int ld = (D + 3) / 4 * 4;
     float* Pb = c.ws.get_t<float>(tag + "ip.P", (size_t)nq * ld, &st);
     float* Qb = c.ws.get_t<float>(tag + "ip.Q", (size_t)nr * ld, &st);
+    float* ph = c.ws.get_t<float>(tag + "ip.ph", nq, &st);
+    float* qh = c.ws.get_t<float>(tag + "ip.qh", nr, &st);
     float* hb = c.ws.get_t<float>(tag + "ip.hb", nr, &st);
     if (!st.good()) return st;
     if (side == 0) {
-        GW_HIP(gwk::launch_lift_bar(P, nq, ldp, D, nullptr, D, Pb, ld, c.stream));
-        GW_HIP(gwk::launch_lift_bar(Q, nr, ldq, E, gamma, D, Qb, ld, c.stream));
+        GW_HIP(gwk::launch_lift_bar(P, nq, ldp, D, nullptr, D, Pb, ld, ph, c.stream));
+        GW_HIP(gwk::launch_lift_bar(Q, nr, ldq, E, gamma, D, Qb, ld, qh, c.stream));
     } else {
-        GW_HIP(gwk::launch_lift_bar(P, nq, ldp, E, gamma, D, Pb, ld, c.stream));
-        GW_HIP(gwk::launch_lift_bar(Q, nr, ldq, D, nullptr, D, Qb, ld, c.stream));
+        GW_HIP(gwk::launch_lift_bar(P, nq, ldp, E, gamma, D, Pb, ld, ph, c.stream));
+        GW_HIP(gwk::launch_lift_bar(Q, nr, ldq, D, nullptr, D, Qb, ld, qh, c.stream));
     }
-    GW_HIP(gwk::launch_interp(Pb, nq, ld, Qb, (int)nr, ld, dl, w, h, eps / 8.0, hb, out, c.stream));
+    GW_HIP(gwk::launch_interp(Pb, nq, ld, Qb, (int)nr, ld, D, ph, qh, w, h, eps / 8.0, hb, out, c.stream));
     return Status::ok();
 }
 
