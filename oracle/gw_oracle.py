@@ -29,6 +29,9 @@ Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
                                                     measures, non-negative; symmetric
                                                     in its two arguments
     landmark_lift, kernel_from_cost, kernel_pca   - full-rank exact embedding
+    full_kpca_features                            - full-rank exact embedding for
+                                                    p = 1/2, 1, 2; p = 2 equals
+                                                    weighted PCA (numpy SVD)
     grad_positions, grad_weights                  - quartic-form envelope,
                                                     central finite differences,
                                                     translation / rotation
@@ -112,6 +115,16 @@ def kernel_pca(k: np.ndarray, dim: int, rel_floor: float = 1e-12):
     lam = np.where(keep, lam, 0.0)
     vec = np.where(keep[None, :], vec, 0.0)
     return lam, vec
+
+
+def full_kpca_features(x: np.ndarray, a: np.ndarray, p: float, dim: int):
+    """Kernel PCA of all n points (Appendix B, "Kernel PCA"): Algorithm 4's
+    kernel of c = |x - x'|^p with weighted double centring by a, its top
+    dim eigenpairs, X_i = V_i sqrt(Lambda).  Returns (X n x dim, Lambda)."""
+    x = np.asarray(x, np.float64)
+    k = kernel_from_cost(power_cost(x, x, p), np.asarray(a, np.float64))
+    lam, vec = kernel_pca(k, dim)
+    return vec * np.sqrt(lam)[None, :], lam
 
 
 @dataclass
