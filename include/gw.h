@@ -196,6 +196,25 @@ gw_status gw_sgw(gw_ctx* ctx,
                  const float* y, int64_t m, int dy, const float* b,
                  const gw_params* params, gw_sgw_result* out);
 
+/* Full-N kernel PCA (Appendix B, "Kernel PCA"; the paper's KeOps + eigsh
+   route for all points): features X (n x D, device, row-major, caller
+   allocated) with X_i = V_i sqrt(Lambda) for the D largest eigenpairs of
+   Algorithm 4's kernel of c(x, x') = |x - x'|^p over all n points, weighted
+   double centring with w (device, > 0, sum 1).  x: n x d device points,
+   1 <= d <= 8, 0 < p <= 2, 1 <= D <= min(256, n - 1).  Matrix-free
+   randomized subspace iteration (Halko, Martinsson, Tropp 2011) with D + 32
+   vectors, n_iter (0..100) power steps and a Rayleigh-Ritz step, in FP64;
+   the start block is SplitMix64 noise of seed.  Eigenvalues at or below
+   1e-12 of the largest give zero columns.  lambda (host, D, nullable)
+   receives the eigenvalues, descending.  Features are centred with w (w
+   spans the kernel's null space).  Eigenvectors are defined up to sign (and
+   rotation inside repeated eigenvalues).  GW_EUNSUPPORTED for d > 8 or
+   n (D + 32) >= 2^31; GW_EINVAL for other sizes out of range, null
+   pointers or invalid inputs; GW_ENUMERIC if the iteration loses rank. */
+gw_status gw_kpca_full(gw_ctx* ctx, const float* x, int64_t n, int d, const float* w,
+                       double p, int D, int n_iter, uint64_t seed,
+                       float* X, double* lambda);
+
 /* ---- Multiscale-GW (Appendix B, "Implementation of Multiscale-GW") ---- */
 
 /* Coarsen of Multiscale-GW: weighted K-Means of the rows of X (n x D,

@@ -158,6 +158,18 @@ class Context:
                                     ctypes.byref(prm), ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in L.GwSgwResult._fields_}
 
+    def kpca_full(self, x, w, p: float = 1.0, D: int = 64, n_iter: int = 10, seed: int = 0):
+        """Full-N kernel PCA of |x - x'|^p (gw_kpca_full): features (n, D)
+        and the D eigenvalues, descending."""
+        x = _dev_f32(x, "x")
+        w = _dev_f32(w, "w")
+        n, d = x.shape
+        X = torch.empty((n, D), dtype=torch.float32, device=x.device)
+        lam = (ctypes.c_double * D)()
+        self._check(self.lib.gw_kpca_full(self.h, _ptr(x), n, d, _ptr(w), float(p), int(D), int(n_iter),
+                                          ctypes.c_uint64(seed), _ptr(X), lam))
+        return X, [float(v) for v in lam]
+
     def kmeans(self, X, w, k: int, n_lloyd: int = 10, seed: int = 0) -> dict:
         """Coarsen of Multiscale-GW (gw_kmeans): weighted K-Means of the rows
         of X (n, D) with weights w (n,).  Returns the non-empty clusters

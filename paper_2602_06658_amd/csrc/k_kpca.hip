@@ -1,0 +1,160 @@
+// Kernels of the full-N kernel PCA (Appendix B, "Kernel PCA" with
+// Algorithm 4's kernel from a CNT cost), run matrix-free by randomized
+// subspace iteration:
+//   - R = C M for C_ij = |x_i - x_j|^p generated on the fly (never stored),
+//     M an n x l block of vectors (column-major FP64), accumulated in FP64;
+//   - the start block: counter-based uniform numbers in [-1, 1);
+//   - the features X_i = V_i sqrt(Lambda) from the Ritz vectors.
+// The double centring of Algorithm 4 is applied outside the product as
+// rank-one corrections, so this kernel only sees the raw cost.
+#include <hip/hip_runtime.h>
+
+#include "gw_kpca.h"
+
+namespace gwk {
+
+constexpr int KP_THREADS = 256;
+constexpr int KP_ROWS = 4;    // rows of C per thread
+constexpr int KP_COLS = 16;   // columns of M per block (gridDim.y covers l)
+constexpr int KP_TJ = 64;     // points j per LDS tile
+
+// pmode: 0 p = 2 (squared distance), 1 p = 1 (distance), 2 general p.
+template <int MAXD>
+__global__ void __launch_bounds__(KP_THREADS) k_kpca_cm(const float* __restrict__ x, int64_t n, int d, int pmode,
+                                                        float half_p, const double* __restrict__ M, int64_t ldm,
+                                                        int l, double* __restrict__ R, int64_t ldr) {
+    __shared__ float xs[KP_TJ * MAXD];
+    __shared__ double ms[KP_TJ * KP_COLS];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.y * KP_COLS;
+    const int64_t i0 = ((int64_t)blockIdx.x * KP_THREADS + tid) * KP_ROWS;
+    float xi[KP_ROWS][MAXD];
+#pragma unroll
+    for (int r = 0; r < KP_ROWS; ++r)
+#pragma unroll
+        for (int dd = 0; dd < MAXD; ++dd) xi[r][dd] = (i0 + r < n && dd < d) ? x[(i0 + r) * d + dd] : 0.f;
+    double acc[KP_ROWS][KP_COLS];
+#pragma unroll
+    for (int r = 0; r < KP_ROWS; ++r)
+#pragma unroll
+        for (int cc = 0; cc < KP_COLS; ++cc) acc[r][cc] = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += KP_TJ) {
+        __syncthreads();
+        for (int e = tid; e < KP_TJ * MAXD; e += KP_THREADS) {
+            const int jj = e / MAXD, dd = e - jj * MAXD;
+            xs[e] = (j0 + jj < n && dd < d) ? x[(j0 + jj) * d + dd] : 0.f;
+        }
+        for (int e = tid; e < KP_TJ * KP_COLS; e += KP_THREADS) {
+            const int cc = e / KP_TJ, jj = e - cc * KP_TJ;
+            ms[jj * KP_COLS + cc] = (j0 + jj < n && c0 + cc < l) ? M[(int64_t)(c0 + cc) * ldm + j0 + jj] : 0.0;
+        }
+        __syncthreads();
+        const int nj = (int)(n - j0 < KP_TJ ? n - j0 : KP_TJ);
+        for (int jj = 0; jj < nj; ++jj) {
+            double cij[KP_ROWS];
+#pragma unroll
+            for (int r = 0; r < KP_ROWS; ++r) {
+                float s = 0.f;
+#pragma unroll
+                for (int dd = 0; dd < MAXD; ++dd) {
+                    const float t = xi[r][dd] - xs[jj * MAXD + dd];
+                    s = fmaf(t, t, s);
+                }
+                float c;
+                if (pmode == 0) c = s;
+                else if (pmode == 1) c = sqrtf(s);
+                else c = s > 0.f ? exp2f(half_p * log2f(s)) : 0.f;
+                cij[r] = (double)c;
+            }
+#pragma unroll
+            for (int cc = 0; cc < KP_COLS; ++cc) {
+                const double mv = ms[jj * KP_COLS + cc];
+#pragma unroll
+                for (int r = 0; r < KP_ROWS; ++r) acc[r][cc] = fma(cij[r], mv, acc[r][cc]);
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < KP_COLS; ++cc)
+#pragma unroll
+        for (int r = 0; r < KP_ROWS; ++r)
+            if (i0 + r < n && c0 + cc < l) R[(int64_t)(c0 + cc) * ldr + i0 + r] = acc[r][cc];
+}
+
+// Omega_ij uniform in [-1, 1) from SplitMix64 of (seed, j * n + i).
+__global__ void k_kpca_start(int64_t n, int l, uint64_t seed, double* Om) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * (int64_t)l) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    Om[e] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+__global__ void k_kpca_widen(const float* __restrict__ a, int64_t n, double* out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)a[i];
+}
+
+// X[i][k] = V[i][l-1-k] sqrt(theta_{l-1-k}), k < D: the D largest Ritz values
+// (V = Q U, column-major n x l, theta ascending); 0 where theta <= floor.
+__global__ void k_kpca_features(const double* __restrict__ V, int64_t ldv, int64_t n, int l, int D,
+                                const double* __restrict__ theta, double floor, float* X, int ldx) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * (int64_t)D) return;
+    const int64_t i = e / D;
+    const int k = (int)(e - i * D);
+    const int col = l - 1 - k;
+    const double th = theta[col];
+    X[i * ldx + k] = th > floor ? (float)(V[(int64_t)col * ldv + i] * sqrt(th)) : 0.f;
+}
+
+static int blocks_for(int64_t count, int threads) { return (int)((count + threads - 1) / threads); }
+
+hipError_t launch_kpca_cm(const float* x, int64_t n, int d, double p, const double* M, int64_t ldm, int l, double* R,
+                          int64_t ldr, hipStream_t stream) {
+    if (n < 1 || l < 1 || d < 1 || d > KPCA_MAX_IN_DIM) return hipErrorInvalidValue;
+    const int pmode = p == 2.0 ? 0 : (p == 1.0 ? 1 : 2);
+    const dim3 grid(blocks_for(n, KP_THREADS * KP_ROWS), (l + KP_COLS - 1) / KP_COLS);
+    if (d <= 4)
+        hipLaunchKernelGGL(k_kpca_cm<4>, grid, dim3(KP_THREADS), 0, stream, x, n, d, pmode, (float)(0.5 * p), M, ldm,
+                           l, R, ldr);
+    else
+        hipLaunchKernelGGL(k_kpca_cm<8>, grid, dim3(KP_THREADS), 0, stream, x, n, d, pmode, (float)(0.5 * p), M, ldm,
+                           l, R, ldr);
+    return hipGetLastError();
+}
+
+hipError_t launch_kpca_start(int64_t n, int l, uint64_t seed, double* Om, hipStream_t stream) {
+    hipLaunchKernelGGL(k_kpca_start, dim3(blocks_for(n * (int64_t)l, 256)), dim3(256), 0, stream, n, l, seed, Om);
+    return hipGetLastError();
+}
+
+hipError_t launch_kpca_widen(const float* a, int64_t n, double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_kpca_widen, dim3(blocks_for(n, 256)), dim3(256), 0, stream, a, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_kpca_features(const double* V, int64_t ldv, int64_t n, int l, int D, const double* theta,
+                                double floor, float* X, int ldx, hipStream_t stream) {
+    hipLaunchKernelGGL(k_kpca_features, dim3(blocks_for(n * (int64_t)D, 256)), dim3(256), 0, stream, V, ldv, n, l, D,
+                       theta, floor, X, ldx);
+    return hipGetLastError();
+}
+
+}  // namespace gwk
+
+namespace gwk {
+
+__global__ void k_kpca_fill(double* p, int64_t n, double v) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_kpca_fill(double* p, int64_t n, double v, hipStream_t stream) {
+    hipLaunchKernelGGL(k_kpca_fill, dim3((int)((n + 255) / 256)), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace gwk
