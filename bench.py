@@ -105,6 +105,9 @@ def parse():
     ap.add_argument("--sgw-only", action="store_true",
                     help="measure only the Sinkhorn-GW divergence (three solves) on the 20k workload")
     ap.add_argument("--sgw-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--kpca", action="store_true",
+                    help="time full-N kernel PCA and compare its embedding with the landmark lifting")
+    ap.add_argument("--kpca-iters", type=int, default=10)
     ap.add_argument("--msgw", action="store_true",
                     help="time Multiscale-GW against the plain solve on the same lifted features")
     ap.add_argument("--msgw-rho", type=float, default=0.1)
@@ -320,6 +323,37 @@ def msgw_bench(args, gwm, torch, X, a, Y, b, prob) -> dict:
     return out
 
 
+def kpca_bench(args, gwm, torch, prob, x, a, X_landmark) -> dict:
+    """Full-N kernel PCA of |x - x'| on all points of the workload (D =
+    args.dim, args.kpca_iters power steps) against the landmark lifting:
+    time, and the distortion of the embedded cost |X_i - X_j|^2 against
+    |x_i - x_j| over 4096 seeded random pairs (relative RMS)."""
+    ctx = gwm.Context()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xf, lam = ctx.kpca_full(x, a, p=prob.p, D=args.dim, n_iter=args.kpca_iters, seed=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rng = np.random.default_rng(77)
+    i = rng.integers(0, prob.n, 4096)
+    j = rng.integers(0, prob.n, 4096)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    xs = x.cpu().numpy().astype(np.float64)
+    c = np.sqrt(((xs[i] - xs[j]) ** 2).sum(1)) ** prob.p
+
+    def distortion(F):
+        F = F.cpu().numpy().astype(np.float64)
+        e = ((F[i] - F[j]) ** 2).sum(1)
+        return float(np.sqrt(np.mean((e - c) ** 2) / np.mean(c ** 2)))
+
+    return {"workload": f"N={prob.n} points in 3-D, |x-x'|, D={args.dim}, {args.kpca_iters} power steps, "
+                        f"block of D+32 vectors", "seconds": dt,
+            "lambda_first": lam[0], "lambda_last": lam[-1],
+            "distortion_full_n": distortion(Xf), "distortion_landmarks": distortion(X_landmark),
+            "landmarks": args.landmarks}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -377,6 +411,9 @@ def main():
 
     if args.msgw:
         print(json.dumps({"msgw": msgw_bench(args, gwm, torch, X, a, Y, b, prob)}), flush=True)
+        return
+    if args.kpca:
+        print(json.dumps({"kpca": kpca_bench(args, gwm, torch, prob, x, a, X)}), flush=True)
         return
 
     ctx = gwm.Context()
