@@ -278,11 +278,13 @@ class GWResult:
     pi: np.ndarray           # final coupling
     eps: float               # last outer temperature
     history: list = field(default_factory=list)
+    n_inner_final: int = 0   # Sinkhorn count of the last outer step
+    doublings: int = 0       # adaptive counts: doublings made
 
 
 def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
            f0=None, g0=None, symmetric=True, record=False, inner_tol=None,
-           anneal_final=False) -> GWResult:
+           anneal_final=False, adaptive=False) -> GWResult:
     """Algorithm 1 (CNT-GW), Section 5, with a fixed number of outer steps.
 
     Per outer step t: Zbar_j = [Gamma_t Y_j, |Y_j|^2/2]; the squared-norm
@@ -295,7 +297,15 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     anneal_final: Sinkhorn annealing in the last outer step only (Appendix
     B.1, "Sinkhorn Annealing"): iteration n = 1..n_inner of that step runs
     at eps_n = eps_T / sqrt(n); the plan, Gamma_T and the returned eps use
-    the last eps_n.  Potentials are in cost units, so nothing is rebased."""
+    the last eps_n.  Potentials are in cost units, so nothing is rebased.
+
+    adaptive: Algorithm 6's adaptive counts applied to CNT-GW (Appendix B,
+    "Adaptive Sinkhorn Iterations", with the lifted squared-norm loss as the
+    base cost): after each outer step the EGW objective L_lift + eps KL of
+    the new plan is compared with that of the previous plan at the same
+    eps; when it is larger (by more than 1e-6 relative) the count doubles,
+    up to 64 n_inner.  The previous plan of step 0 is a x b when gamma0 is
+    None; with a given gamma0 the first comparison is after step 1."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     X = np.asarray(X, np.float64)
@@ -308,16 +318,20 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     gamma_prev = gamma
     pi = None
     eps_list = list(eps_schedule(eps_start, eps_end, n_outer))
+    n_in, doublings = int(n_inner), 0
+    prev = None
+    if adaptive and gamma0 is None:
+        prev = (lifted_loss(X, Y, a, b, a[:, None] * b[None, :]), 0.0)
     for t, eps in enumerate(eps_list):
         zbar = np.concatenate([Y @ gamma.T, 0.5 * np.sum(Y * Y, axis=1, keepdims=True)], axis=1)
         cbar = sqdist(xbar, zbar)
         if anneal_final and t == n_outer - 1:
-            for it in range(1, n_inner + 1):
+            for it in range(1, n_in + 1):
                 f, g = sinkhorn(a, b, cbar, eps / np.sqrt(it) / 8.0, 1, f, g, symmetric)
-            eps = eps / np.sqrt(max(n_inner, 1))
+            eps = eps / np.sqrt(max(n_in, 1))
             eps_list[-1] = eps
         elif inner_tol is None:
-            f, g = sinkhorn(a, b, cbar, eps / 8.0, n_inner, f, g, symmetric)
+            f, g = sinkhorn(a, b, cbar, eps / 8.0, n_in, f, g, symmetric)
         else:
             f, g = sinkhorn_converged(a, b, cbar, eps / 8.0, f, g, tol=inner_tol)
         epsp = eps / 8.0
@@ -329,7 +343,15 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
             hist.append({"eps": float(eps), "gamma": new_gamma.copy(),
                          "pi": pi.copy(), "f": f.copy(), "g": g.copy()})
         gamma_prev, gamma = gamma, new_gamma
-    return GWResult(f, g, gamma, gamma_prev, pi, float(eps_list[-1]), hist)
+        if adaptive and t < n_outer - 1:
+            cur = (lifted_loss(X, Y, a, b, pi), kl_divergence(pi, a, b))
+            if prev is not None:
+                e_new, e_old = cur[0] + eps * cur[1], prev[0] + eps * prev[1]
+                if e_new - e_old > 1e-6 * abs(e_old) and n_in < 64 * n_inner:
+                    n_in = min(2 * n_in, 64 * n_inner)
+                    doublings += 1
+            prev = cur
+    return GWResult(f, g, gamma, gamma_prev, pi, float(eps_list[-1]), hist, n_in, doublings)
 
 
 # --------------------------------------------------------------------------
