@@ -101,7 +101,19 @@ typedef struct {
                                   the plan, Gamma_T and the reported eps use the
                                   last of them; 0: off.  Not applied when
                                   tol_gamma stops the loop earlier. */
-    int32_t reserved;          /* must be 0 */
+    int32_t adaptive_inner;    /* 1: Algorithm 6's adaptive Sinkhorn counts:
+                                  n_inner is the first step's count, and it
+                                  doubles after a step whose coupling has a
+                                  larger EGW objective (at that step's eps)
+                                  than the previous coupling, by more than
+                                  1e-6 max(|EGW|, C), C the constant of Lemma
+                                  C.1 (the previous coupling of step
+                                  0 is a x b when gamma0 is NULL, none
+                                  otherwise); capped at 64 x n_inner.  Each
+                                  outer step then runs the FP64 check (one
+                                  extra N x M evaluation and a readback).
+                                  gw_solve only (the server rejects it).
+                                  0: fixed counts. */
 } gw_params;
 
 typedef struct {
@@ -122,6 +134,8 @@ typedef struct {
     int32_t dim_x;             /* D, lifted source dimension */
     int32_t dim_y;             /* E */
     int32_t safe_iters;        /* Sinkhorn iterations that ran max-shifted */
+    int32_t n_inner_final;     /* Sinkhorn count of the last outer step */
+    int32_t inner_doublings;   /* adaptive_inner: doublings made */
 } gw_result;
 
 /* Create a context on HIP device `device`, ordering all work on `hip_stream`

@@ -303,8 +303,9 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     "Adaptive Sinkhorn Iterations", with the lifted squared-norm loss as the
     base cost): after each outer step the EGW objective L_lift + eps KL of
     the new plan is compared with that of the previous plan at the same
-    eps; when it is larger (by more than 1e-6 relative) the count doubles,
-    up to 64 n_inner.  The previous plan of step 0 is a x b when gamma0 is
+    eps; when it is larger by more than 1e-6 max(|EGW|, C) (C the constant
+    of Lemma C.1, the scale of the terms the loss is a difference of) the
+    count doubles, up to 64 n_inner.  The previous plan of step 0 is a x b when gamma0 is
     None; with a given gamma0 the first comparison is after step 1."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -320,6 +321,7 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     eps_list = list(eps_schedule(eps_start, eps_end, n_outer))
     n_in, doublings = int(n_inner), 0
     prev = None
+    c_scale = constant_c(X, Y, a, b) if adaptive else 0.0
     if adaptive and gamma0 is None:
         prev = (lifted_loss(X, Y, a, b, a[:, None] * b[None, :]), 0.0)
     for t, eps in enumerate(eps_list):
@@ -347,7 +349,7 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
             cur = (lifted_loss(X, Y, a, b, pi), kl_divergence(pi, a, b))
             if prev is not None:
                 e_new, e_old = cur[0] + eps * cur[1], prev[0] + eps * prev[1]
-                if e_new - e_old > 1e-6 * abs(e_old) and n_in < 64 * n_inner:
+                if e_new - e_old > 1e-6 * max(abs(e_old), c_scale) and n_in < 64 * n_inner:
                     n_in = min(2 * n_in, 64 * n_inner)
                     doublings += 1
             prev = cur

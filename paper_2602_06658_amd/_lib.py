@@ -34,7 +34,7 @@ class GwParams(ctypes.Structure):
         ("use_init_potentials", ctypes.c_int32),
         ("tol_gamma", ctypes.c_double),
         ("anneal_final", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("adaptive_inner", ctypes.c_int32),
     ]
 
 
@@ -55,6 +55,8 @@ class GwResult(ctypes.Structure):
         ("dim_x", ctypes.c_int32),
         ("dim_y", ctypes.c_int32),
         ("safe_iters", ctypes.c_int32),
+        ("n_inner_final", ctypes.c_int32),
+        ("inner_doublings", ctypes.c_int32),
     ]
 
 

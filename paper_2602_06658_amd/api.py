@@ -29,7 +29,8 @@ def _ptr(t):
 
 
 def make_params(eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True, precision="fp32",
-                mode="auto", use_init_potentials=False, tol_gamma=0.0, anneal_final=False) -> L.GwParams:
+                mode="auto", use_init_potentials=False, tol_gamma=0.0, anneal_final=False,
+                adaptive_inner=False) -> L.GwParams:
     p = L.GwParams()
     p.eps_start = float(eps_start)
     p.eps_end = float(eps_start if eps_end is None else eps_end)
@@ -41,7 +42,7 @@ def make_params(eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
     p.use_init_potentials = 1 if use_init_potentials else 0
     p.tol_gamma = float(tol_gamma)
     p.anneal_final = 1 if anneal_final else 0
-    p.reserved = 0
+    p.adaptive_inner = 1 if adaptive_inner else 0
     return p
 
 
@@ -52,6 +53,7 @@ def _result_dict(r: L.GwResult, f, g, gamma) -> dict:
         "marginal_err": r.marginal_err, "constant_c": r.constant_c, "sum_pi_nm": r.sum_pi_nm,
         "gamma_step": r.gamma_step, "eps_final": r.eps_final, "outer_done": r.outer_done,
         "dim_x": r.dim_x, "dim_y": r.dim_y, "safe_iters": r.safe_iters,
+        "n_inner_final": r.n_inner_final, "inner_doublings": r.inner_doublings,
     }
 
 
@@ -128,7 +130,7 @@ class Context:
 
     def solve(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
               precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, tol_gamma=0.0,
-              anneal_final=False) -> dict:
+              anneal_final=False, adaptive_inner=False) -> dict:
         x, a, y, b = self._prep(x, a, y, b)
         n, dx = x.shape
         m, dy = y.shape
@@ -138,7 +140,7 @@ class Context:
         gamma = torch.empty((D, E), dtype=torch.float32, device=x.device)
         g0t = None if gamma0 is None else _dev_f32(gamma0, "gamma0")
         prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode,
-                          f0 is not None and g0 is not None, tol_gamma, anneal_final)
+                          f0 is not None and g0 is not None, tol_gamma, anneal_final, adaptive_inner)
         r = L.GwResult()
         r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
         self._check(self.lib.gw_solve(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),

@@ -184,7 +184,8 @@ static Status check_params(const gw_params* prm) {
     if (prm->symmetric != 0 && prm->symmetric != 1) return fail(GW_EINVAL, "symmetric must be 0 or 1");
     if (!(prm->tol_gamma >= 0.0)) return fail(GW_EINVAL, "tol_gamma must be >= 0");
     if (prm->anneal_final != 0 && prm->anneal_final != 1) return fail(GW_EINVAL, "anneal_final must be 0 or 1");
-    if (prm->reserved != 0) return fail(GW_EINVAL, "reserved must be 0");
+    if (prm->adaptive_inner != 0 && prm->adaptive_inner != 1)
+        return fail(GW_EINVAL, "adaptive_inner must be 0 or 1");
     return Status::ok();
 }
 
@@ -307,6 +308,10 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
     prm_ = prm;
     n_ = n;
     m_ = m;
+    n_inner_cur_ = prm.n_inner;
+    doublings_ = 0;
+    gamma0_given_ = gamma0 != nullptr;
+    have_prev_ = have_c_ = false;
     dx_ = dx;
     dy_ = dy;
     x_ = x;
@@ -571,11 +576,57 @@ Status Solve::outer_step() {
     if (done_) return Status::ok();
     GW_TRY(begin_outer());
     // Sinkhorn at eps_t / 8 (Algorithm 3 or 2), warm-started
-    for (int k = 0; k < prm_.n_inner; ++k) {
+    for (int k = 0; k < n_inner_cur_; ++k) {
         GW_TRY(before_inner(k));
         GW_TRY(inner_iteration(k));
     }
-    return end_outer();
+    GW_TRY(end_outer());
+    if (prm_.adaptive_inner && !done_) GW_TRY(adaptive_step());
+    return Status::ok();
+}
+
+// Algorithm 6 (adaptive Sinkhorn iterations) for CNT-GW: the EGW objective
+// L_lift + eps KL of the new coupling against that of the previous one, both
+// at this step's eps; a value larger by more than 1e-6 max(|EGW|, C) (C of
+// Lemma C.1, the scale of the terms L_lift is a difference of) means the
+// inner solve was too short, and the count doubles.  L_lift = C - 8 |Gamma_{t+1}|^2 - 4 sum pi n m comes from
+// the covariance pass, KL from the FP64 check of the same coupling.
+Status Solve::adaptive_step() {
+    GW_TRY(enqueue_check());
+    const size_t nmx = 2 + (size_t)D_ * D_ + D_, nmy = 2 + (size_t)E_ * E_ + E_;
+    std::vector<double> hs(16), mx, my;
+    GW_HIP(hipMemcpyAsync(hs.data(), scal_, 16 * sizeof(double), hipMemcpyDeviceToHost, st_));
+    if (!have_c_) {
+        mx.resize(nmx);
+        my.resize(nmy);
+        GW_HIP(hipMemcpyAsync(mx.data(), momx_, nmx * sizeof(double), hipMemcpyDeviceToHost, st_));
+        GW_HIP(hipMemcpyAsync(my.data(), momy_, nmy * sizeof(double), hipMemcpyDeviceToHost, st_));
+    }
+    GW_HIP(hipStreamSynchronize(st_));
+    if (!have_c_) {
+        c_const_ = lemma_c1_constant(mx.data(), D_, my.data(), E_);
+        have_c_ = true;
+        if (!gamma0_given_) {
+            // pi^0 = a x b: Gamma_0 = 0 for centred features, KL = 0
+            prev_loss_ = c_const_ - 4.0 * mx[0] * my[0];
+            prev_kl_ = 0.0;
+            have_prev_ = true;
+        }
+    }
+    const double loss = c_const_ - 8.0 * hs[2] - 4.0 * hs[1];
+    const double kl = hs[5];
+    if (!std::isfinite(loss) || !std::isfinite(kl)) return fail(GW_ENUMERIC, "non-finite EGW objective");
+    if (have_prev_) {
+        const double e_new = loss + eps_t_ * kl, e_old = prev_loss_ + eps_t_ * prev_kl_;
+        if (e_new - e_old > 1e-6 * std::max(std::fabs(e_old), c_const_) && n_inner_cur_ < 64 * prm_.n_inner) {
+            n_inner_cur_ = std::min(2 * n_inner_cur_, 64 * prm_.n_inner);
+            ++doublings_;
+        }
+    }
+    prev_loss_ = loss;
+    prev_kl_ = kl;
+    have_prev_ = true;
+    return Status::ok();
 }
 
 Status Solve::before_inner(int k) {
@@ -639,26 +690,7 @@ Status Solve::finish(gw_result* out) {
 
 Status Solve::finish_enqueue(gw_result* out) {
     Status st;
-    auto& ws = c_.ws;
-    // FP64 check of the final coupling (f_T, g_T, Gamma_{T-1})
-    double* r64 = ws.get_t<double>(tag_ + "r64", n_, &st);
-    double* kl64 = ws.get_t<double>(tag_ + "kl64", n_, &st);
-    double* c64 = ws.get_t<double>(tag_ + "c64", m_, &st);
-    if (!st.good()) return st;
-    c_.prof.begin(GW_PROF_CHECK, st_);
-    if (geo_.path == 1) {
-        const float kap = (float)kappa_;
-        GW_HIP(gwk::launch_check64_direct(D_, X_, xn_, U_[pa_], Ul_[pa_], Zs_, ym_, V_[pb_], Vl_[pb_], kap, n_, m_,
-                                          la2_, lb2_, r64, kl64, st_));
-        GW_HIP(gwk::launch_check64_direct(D_, Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_, U_[pa_], Ul_[pa_], kap, m_, n_,
-                                          lb2_, nullptr, c64, nullptr, st_));
-    } else {
-        GW_HIP(gwk::launch_check64(prec_, D_, packA_[pa_], packB_[pb_], n_, m_, la2_, lb2_, chk_, r64, kl64, c64,
-                                   st_));
-    }
-    GW_HIP(gwk::launch_check_final(r64, kl64, n_, a_, c64, m_, b_, asum_, bsum_, scal_, st_));
-    c_.prof.end(st_);
-    c_.prof.entries = n_ * m_;
+    GW_TRY(enqueue_check());
     // outputs: potentials back in Algorithm 1's convention (cost units)
     if (geo_.path == 1) {
         if (out->f) GW_HIP(gwk::launch_epilogue(n_, U_[pa_], Ul_[pa_], la2_, nullptr, nullptr, 0, kappa_, out->f, st_));
@@ -682,6 +714,43 @@ Status Solve::finish_enqueue(gw_result* out) {
     return Status::ok();
 }
 
+// FP64 check of the current coupling (f_t, g_t, Gamma_{t-1}): row sums, KL
+// and column sums, reduced into scal_[4] (Err) and scal_[5] (KL).
+Status Solve::enqueue_check() {
+    Status st;
+    auto& ws = c_.ws;
+    double* r64 = ws.get_t<double>(tag_ + "r64", n_, &st);
+    double* kl64 = ws.get_t<double>(tag_ + "kl64", n_, &st);
+    double* c64 = ws.get_t<double>(tag_ + "c64", m_, &st);
+    if (!st.good()) return st;
+    c_.prof.begin(GW_PROF_CHECK, st_);
+    if (geo_.path == 1) {
+        const float kap = (float)kappa_;
+        GW_HIP(gwk::launch_check64_direct(D_, X_, xn_, U_[pa_], Ul_[pa_], Zs_, ym_, V_[pb_], Vl_[pb_], kap, n_, m_,
+                                          la2_, lb2_, r64, kl64, st_));
+        GW_HIP(gwk::launch_check64_direct(D_, Zs_, ym_, V_[pb_], Vl_[pb_], X_, xn_, U_[pa_], Ul_[pa_], kap, m_, n_,
+                                          lb2_, nullptr, c64, nullptr, st_));
+    } else {
+        GW_HIP(gwk::launch_check64(prec_, D_, packA_[pa_], packB_[pb_], n_, m_, la2_, lb2_, chk_, r64, kl64, c64,
+                                   st_));
+    }
+    GW_HIP(gwk::launch_check_final(r64, kl64, n_, a_, c64, m_, b_, asum_, bsum_, scal_, st_));
+    c_.prof.end(st_);
+    c_.prof.entries = n_ * m_;
+    return Status::ok();
+}
+
+// Lemma C.1: C = iint|x-x'|^4 + iint|y-y'|^4 - 4 s_x s_y; for centred
+// measures iint |x - x'|^4 = 2 m4 + 4 |Sigma|^2 + 2 s^2 (moments: s, m4, Sigma).
+double lemma_c1_constant(const double* mx, int D, const double* my, int E) {
+    auto cpart = [](const double* mo, int d) {
+        double s = mo[0], m4 = mo[1], sig2 = 0.0;
+        for (int k = 0; k < d * d; ++k) sig2 += mo[2 + k] * mo[2 + k];
+        return 2.0 * m4 + 4.0 * sig2 + 2.0 * s * s;
+    };
+    return cpart(mx, D) + cpart(my, E) - 4.0 * mx[0] * my[0];
+}
+
 Status Solve::finish_collect(gw_result* out) {
     const size_t nmx = 2 + (size_t)D_ * D_ + D_, nmy = 2 + (size_t)E_ * E_ + E_;
     Status st;
@@ -690,14 +759,7 @@ Status Solve::finish_collect(gw_result* out) {
     const double* mx = hs + 16;
     const double* my = hs + 16 + nmx;
     const int* hctl = (const int*)(hs + 16 + nmx + nmy);
-    auto cpart = [](const double* mo, int d) {
-        double s = mo[0], m4 = mo[1], sig2 = 0.0;
-        for (int k = 0; k < d * d; ++k) sig2 += mo[2 + k] * mo[2 + k];
-        return 2.0 * m4 + 4.0 * sig2 + 2.0 * s * s;
-    };
-    // Lemma C.1: C = iint|x-x'|^4 + iint|y-y'|^4 - 4 s_x s_y; for centred
-    // measures iint |x - x'|^4 = 2 m4 + 4 |Sigma|^2 + 2 s^2.
-    const double C = cpart(mx, D_) + cpart(my, E_) - 4.0 * mx[0] * my[0];
+    const double C = lemma_c1_constant(mx, D_, my, E_);
     out->constant_c = C;
     out->sum_pi_nm = hs[1];
     out->loss_lift = C - 8.0 * hs[2] - 4.0 * hs[1];
@@ -710,6 +772,8 @@ Status Solve::finish_collect(gw_result* out) {
     out->dim_x = D_;
     out->dim_y = E_;
     out->safe_iters = hctl[CTL_SAFE_ITERS];
+    out->n_inner_final = n_inner_cur_;
+    out->inner_doublings = doublings_;
     if (hctl[CTL_NUMERIC] || !std::isfinite(out->loss_lift) || !std::isfinite(out->kl))
         return fail(GW_ENUMERIC, "non-finite values in the Sinkhorn iteration");
     return Status::ok();

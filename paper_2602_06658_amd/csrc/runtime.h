@@ -191,7 +191,7 @@ class Solve {
         pa_ ^= 1;
         pb_ ^= 1;
     }
-    int n_inner() const { return prm_.n_inner; }
+    int n_inner() const { return n_inner_cur_; }
     // Device bytes of the solve's buffers for these sizes (nothing allocated);
     // 0 if the sizes are rejected.
     static size_t plan_bytes(Ctx& c, int64_t n, int dx, int64_t m, int dy, const gw_params& prm);
@@ -202,6 +202,8 @@ class Solve {
 
    private:
     Status prologue(int first);
+    Status enqueue_check();
+    Status adaptive_step();
     Status configure(int64_t n, int dx, int64_t m, int dy, const gw_params& prm);
     Status buffers(bool dry = false);
     void make_half(int do_rows, int do_cols, float step, gwk::Operands& op, gwk::CombineArgs& ca);
@@ -258,7 +260,14 @@ class Solve {
     double *momx_ = nullptr, *momy_ = nullptr, *mompart_ = nullptr;
     double* chk_ = nullptr;  // FP64 check partials (MFMA path)
     int cov_tw_ = 0;
+    // adaptive Sinkhorn counts (Algorithm 6)
+    int n_inner_cur_ = 0, doublings_ = 0;
+    bool gamma0_given_ = false, have_prev_ = false, have_c_ = false;
+    double prev_loss_ = 0.0, prev_kl_ = 0.0, c_const_ = 0.0;
 };
+
+// The constant C(alpha, beta) of Lemma C.1 from the FP64 moments of both sides.
+double lemma_c1_constant(const double* mx, int D, const double* my, int E);
 
 }  // namespace gwr
 

@@ -182,6 +182,7 @@ gwr::Status start(gw_server* s, Request* q) {
     q->solve = std::make_unique<gwr::Solve>(c, "q.");
     const gw_request& r = q->r;
     GW_TRY(gwr::validate_inputs(c, r.x, r.n, r.dx, r.a, r.y, r.m, r.dy, r.b, &r.params, "q."));
+    if (r.params.adaptive_inner) return gwr::fail(GW_EUNSUPPORTED, "adaptive_inner is not served");
     GW_TRY(q->solve->setup(r.x, r.n, r.dx, r.a, r.y, r.m, r.dy, r.b, r.params, r.gamma0, nullptr, nullptr, r.penalty,
                            r.penalty, c.stream));
     GW_HIP(hipEventRecord(q->slot->ev, c.stream));

@@ -24,7 +24,7 @@ class Server:
 
     def submit(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                precision="fp32", mode="auto", penalty="sqeuclid", p=1.0, lifted_dim=0, n_landmarks=0,
-               seed=0, anneal_final=False, gamma0=None) -> int:
+               seed=0, anneal_final=False, gamma0=None, adaptive_inner=False) -> int:
         """Queue one solve; returns its ticket.  The tensors stay referenced
         until the result is collected.  Landmarks of the |x - x'|^p penalty
         use seed for the source and seed + 1 for the target."""
@@ -41,7 +41,7 @@ class Server:
         r.x, r.n, r.dx, r.a = x.data_ptr(), n, dx, a.data_ptr()
         r.y, r.m, r.dy, r.b = y.data_ptr(), m, dy, b.data_ptr()
         r.params = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode,
-                               anneal_final=anneal_final)
+                               anneal_final=anneal_final, adaptive_inner=adaptive_inner)
         r.penalty, r.p, r.lifted_dim, r.n_landmarks, r.seed = pen, float(p), int(lifted_dim), int(n_landmarks), seed
         r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
         g0 = None
