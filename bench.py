@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--sgw-only", action="store_true",
                     help="measure only the Sinkhorn-GW divergence (three solves) on the 20k workload")
     ap.add_argument("--sgw-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--adaptive", action="store_true",
+                    help="fixed against adaptive Sinkhorn counts on the 20,000-point workload")
     ap.add_argument("--kpca", action="store_true",
                     help="time full-N kernel PCA and compare its embedding with the landmark lifting")
     ap.add_argument("--kpca-iters", type=int, default=10)
@@ -226,6 +228,45 @@ def sgw_bench(args, gwm, torch, dev) -> dict:
                         f"eps {prob.eps_start}->{prob.eps_end}, {prob.n_outer}x{prob.n_inner}, {args.sgw_precision}",
             "seconds": dt, "entries_per_s": entries / dt, "sgw": res["sgw"], "gw_xy": res["gw_xy"],
             "gw_xx": res["gw_xx"], "gw_yy": res["gw_yy"], "marginal_err": res["marginal_err"]}
+
+
+def adaptive_bench(args, gwm, torch, dev) -> dict:
+    """Algorithm 6's adaptive counts on the 20,000-point workload (3-D
+    mixture, target a noisy rigid motion, |x - x'| lifted to D = 32 with 2048
+    landmarks, eps 0.1 -> 0.005 over 30 outer steps, BF16): the fixed count
+    100 against adaptive counts started at 10 and 25."""
+    from workloads import config2_fp32, landmark_indices
+
+    prob = config2_fp32()
+    t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
+    x, a, y, b = t(prob.x), t(prob.a), t(prob.y), t(prob.b)
+    ctx = gwm.Context()
+    for side, (npts, seed) in enumerate(((prob.n, 2101), (prob.m, 2102))):
+        ctx.set_penalty(side, "power", p=prob.p, lifted_dim=prob.lifted_dim, n_landmarks=2048)
+        ctx.set_landmarks(side, landmark_indices(npts, 2048, seed))
+    X, Y = ctx.lift(0, x, a), ctx.lift(1, y, b)
+    fctx = gwm.Context()
+    fctx.set_penalty(2, "features")
+    out = {"workload": f"gmm3d N=M={prob.n}, |x-x'| lifted to D={prob.lifted_dim} (2048 landmarks), "
+                       f"eps {prob.eps_start}->{prob.eps_end}, {prob.n_outer} outer steps, bf16"}
+    cases = (("fixed_100", 100, False, prob.eps_end), ("adaptive_from_10", 10, True, prob.eps_end),
+             ("adaptive_from_25", 25, True, prob.eps_end), ("fixed_eps_0.02_fixed_100", 100, False, None),
+             ("fixed_eps_0.02_adaptive_from_10", 10, True, None))
+    for name, nin, adaptive, eps_end in cases:
+        e0 = prob.eps_start if eps_end is not None else 0.02
+        e1 = eps_end if eps_end is not None else 0.02
+        run = lambda: fctx.solve(X, a, Y, b, e0, e1, prob.n_outer, nin,  # noqa: E731
+                                 precision="bf16", adaptive_inner=adaptive)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = run()
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "egw_objective": r["egw_objective"],
+                     "loss_lift": r["loss_lift"], "marginal_err": r["marginal_err"],
+                     "n_inner_final": r["n_inner_final"], "doublings": r["inner_doublings"]}
+        print(f"adaptive bench: {name} done", file=sys.stderr, flush=True)
+    return out
 
 
 def multiseed_bench(args, gwm, torch, dev) -> dict:
@@ -371,6 +412,9 @@ def main():
         return
     if args.sgw_only:
         print(json.dumps({"sgw": sgw_bench(args, gwm, torch, dev)}), flush=True)
+        return
+    if args.adaptive:
+        print(json.dumps({"adaptive": adaptive_bench(args, gwm, torch, dev)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(args, gwm, torch, dev)}), flush=True)
