@@ -1,6 +1,7 @@
 // Kernels of the full-N kernel PCA (Appendix B, "Kernel PCA" with
 // Algorithm 4's kernel from a CNT cost), run matrix-free by randomized
-// subspace iteration:
+// subspace iteration (blocks of up to 16 columns in k_kpca_cm, wider ones in
+// k_kpca_cm_wide):
 //   - R = C M for C_ij = |x_i - x_j|^p generated on the fly (never stored),
 //     M an n x l block of vectors (column-major FP64), accumulated in FP64;
 //   - the start block: counter-based uniform numbers in [-1, 1);
@@ -81,6 +82,85 @@ __global__ void __launch_bounds__(KP_THREADS) k_kpca_cm(const float* __restrict_
             if (i0 + r < n && c0 + cc < l) R[(int64_t)(c0 + cc) * ldr + i0 + r] = acc[r][cc];
 }
 
+// Wide form for blocks of more than 16 columns: a workgroup of 6 waves covers
+// 256 rows x 96 columns.  The costs of a 256 x 32 tile are computed once into
+// LDS (instead of once per 16-column group); wave w owns columns 16 w..16 w+15
+// of the workgroup's 96 and thread t of the wave rows 4 t..4 t+3, so the four
+// costs of a point are one 16-byte LDS read and the M values are broadcasts.
+constexpr int KW_ROWS = 256, KW_COLS = 96, KW_TJ = 32, KW_THREADS = 384;
+
+template <int MAXD>
+__global__ void __launch_bounds__(KW_THREADS) k_kpca_cm_wide(const float* __restrict__ x, int64_t n, int d,
+                                                             int pmode, float half_p, const double* __restrict__ M,
+                                                             int64_t ldm, int l, double* __restrict__ R,
+                                                             int64_t ldr) {
+    __shared__ float xr[KW_ROWS * MAXD];
+    __shared__ float xs[KW_TJ * MAXD];
+    __shared__ __attribute__((aligned(16))) float cs[KW_TJ * KW_ROWS];
+    __shared__ __attribute__((aligned(16))) double ms[KW_TJ * KW_COLS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, grp = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * KW_ROWS;
+    const int col0 = blockIdx.y * KW_COLS;
+    for (int e = tid; e < KW_ROWS * MAXD; e += KW_THREADS) {
+        const int r = e / MAXD, dd = e - r * MAXD;
+        xr[e] = (row0 + r < n && dd < d) ? x[(row0 + r) * d + dd] : 0.f;
+    }
+    double acc[4][16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc[r][cc] = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += KW_TJ) {
+        __syncthreads();
+        for (int e = tid; e < KW_TJ * MAXD; e += KW_THREADS) {
+            const int jj = e / MAXD, dd = e - jj * MAXD;
+            xs[e] = (j0 + jj < n && dd < d) ? x[(j0 + jj) * d + dd] : 0.f;
+        }
+        for (int e = tid; e < KW_TJ * KW_COLS; e += KW_THREADS) {
+            const int cc = e / KW_TJ, jj = e - cc * KW_TJ;
+            ms[jj * KW_COLS + cc] = (j0 + jj < n && col0 + cc < l) ? M[(int64_t)(col0 + cc) * ldm + j0 + jj] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < KW_TJ * KW_ROWS; e += KW_THREADS) {
+            const int jj = e / KW_ROWS, r = e - jj * KW_ROWS;
+            float s = 0.f;
+#pragma unroll
+            for (int dd = 0; dd < MAXD; ++dd) {
+                const float t = xr[r * MAXD + dd] - xs[jj * MAXD + dd];
+                s = fmaf(t, t, s);
+            }
+            float c;
+            if (pmode == 0) c = s;
+            else if (pmode == 1) c = sqrtf(s);
+            else c = s > 0.f ? exp2f(half_p * log2f(s)) : 0.f;
+            cs[jj * KW_ROWS + r] = c;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int jj = 0; jj < KW_TJ; ++jj) {
+            const float4 c4 = *(const float4*)&cs[jj * KW_ROWS + lane * 4];
+            const double cr[4] = {(double)c4.x, (double)c4.y, (double)c4.z, (double)c4.w};
+            const double* mrow = &ms[jj * KW_COLS + grp * 16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) {
+                const double mv = mrow[cc];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][cc] = fma(cr[r], mv, acc[r][cc]);
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+        const int col = col0 + grp * 16 + cc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = row0 + lane * 4 + r;
+            if (i < n && col < l) R[(int64_t)col * ldr + i] = acc[r][cc];
+        }
+    }
+}
+
 // Omega_ij uniform in [-1, 1) from SplitMix64 of (seed, j * n + i).
 __global__ void k_kpca_start(int64_t n, int l, uint64_t seed, double* Om) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -116,6 +196,16 @@ hipError_t launch_kpca_cm(const float* x, int64_t n, int d, double p, const doub
                           int64_t ldr, hipStream_t stream) {
     if (n < 1 || l < 1 || d < 1 || d > KPCA_MAX_IN_DIM) return hipErrorInvalidValue;
     const int pmode = p == 2.0 ? 0 : (p == 1.0 ? 1 : 2);
+    if (l > KP_COLS) {
+        const dim3 gw(blocks_for(n, KW_ROWS), (l + KW_COLS - 1) / KW_COLS);
+        if (d <= 4)
+            hipLaunchKernelGGL(k_kpca_cm_wide<4>, gw, dim3(KW_THREADS), 0, stream, x, n, d, pmode, (float)(0.5 * p),
+                               M, ldm, l, R, ldr);
+        else
+            hipLaunchKernelGGL(k_kpca_cm_wide<8>, gw, dim3(KW_THREADS), 0, stream, x, n, d, pmode, (float)(0.5 * p),
+                               M, ldm, l, R, ldr);
+        return hipGetLastError();
+    }
     const dim3 grid(blocks_for(n, KP_THREADS * KP_ROWS), (l + KP_COLS - 1) / KP_COLS);
     if (d <= 4)
         hipLaunchKernelGGL(k_kpca_cm<4>, grid, dim3(KP_THREADS), 0, stream, x, n, d, pmode, (float)(0.5 * p), M, ldm,
