@@ -20,5 +20,13 @@ hipError_t launch_kpca_widen(const float* a, int64_t n, double* out, hipStream_t
 hipError_t launch_kpca_features(const double* V, int64_t ldv, int64_t n, int l, int D, const double* theta,
                                 double floor, float* X, int ldx, hipStream_t stream);
 hipError_t launch_kpca_fill(double* p, int64_t n, double v, hipStream_t stream);
+// G (column-major l x l) = A^T B for column-major n x l blocks A, B (l <= 288),
+// summed per chunk of rows into part (kpca_gram_part_doubles) and reduced in
+// chunk order.
+size_t kpca_gram_part_doubles(int64_t n, int l);
+hipError_t launch_kpca_gram(const double* A, const double* B, int64_t n, int l, double* part, double* G,
+                            hipStream_t stream);
+// T = Y W for a column-major n x l block Y and l x l matrix W (l <= 288).
+hipError_t launch_kpca_rowmul(const double* Y, int64_t n, int l, const double* W, double* T, hipStream_t stream);
 
 }  // namespace gwk

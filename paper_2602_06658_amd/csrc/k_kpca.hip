@@ -248,3 +248,120 @@ hipError_t launch_kpca_fill(double* p, int64_t n, double v, hipStream_t stream) 
 }
 
 }  // namespace gwk
+
+namespace gwk {
+
+// ---------------------------------------------------------------------------
+// Tall-skinny products of the subspace iteration (n x l blocks, column-major,
+// l small): G = A^T B and T = Y W.  Both are bound by reading the n x l
+// blocks once; the Gram matrix is summed per chunk of rows and the chunks are
+// reduced in a fixed order, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+
+constexpr int KG_ROWS = 2048;   // rows per chunk
+constexpr int KG_SUB = 32;      // rows per LDS stage
+constexpr int KG_B = 96;        // output block edge (16 x 16 threads, 6 x 6 each)
+
+// part[chunk][bp][bq] 96 x 96 block (row-major, padded) of A^T B over the chunk.
+__global__ void __launch_bounds__(256) k_kpca_gram_part(const double* __restrict__ A, const double* __restrict__ B,
+                                                        int64_t n, int l, double* part, int nb) {
+    __shared__ double as[KG_SUB * KG_B];
+    __shared__ double bs[KG_SUB * KG_B];
+    const int tid = threadIdx.x, tp = tid >> 4, tq = tid & 15;
+    const int bp = blockIdx.y, bq = blockIdx.z;
+    const int64_t r0 = (int64_t)blockIdx.x * KG_ROWS;
+    double acc[6][6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+#pragma unroll
+        for (int v = 0; v < 6; ++v) acc[u][v] = 0.0;
+    for (int s0 = 0; s0 < KG_ROWS; s0 += KG_SUB) {
+        __syncthreads();
+        for (int e = tid; e < KG_SUB * KG_B; e += 256) {
+            const int c = e / KG_SUB, r = e - c * KG_SUB;
+            const int64_t i = r0 + s0 + r;
+            const int ca = bp * KG_B + c, cb = bq * KG_B + c;
+            as[r * KG_B + c] = (i < n && ca < l) ? A[(int64_t)ca * n + i] : 0.0;
+            bs[r * KG_B + c] = (i < n && cb < l) ? B[(int64_t)cb * n + i] : 0.0;
+        }
+        __syncthreads();
+        for (int r = 0; r < KG_SUB; ++r) {
+            double av[6], bv[6];
+#pragma unroll
+            for (int u = 0; u < 6; ++u) av[u] = as[r * KG_B + tp * 6 + u];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) bv[v] = bs[r * KG_B + tq * 6 + v];
+#pragma unroll
+            for (int u = 0; u < 6; ++u)
+#pragma unroll
+                for (int v = 0; v < 6; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        }
+    }
+    double* out = part + (((int64_t)blockIdx.x * nb + bp) * nb + bq) * (KG_B * KG_B);
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+#pragma unroll
+        for (int v = 0; v < 6; ++v) out[(tp * 6 + u) * KG_B + tq * 6 + v] = acc[u][v];
+}
+
+// G (column-major l x l) = sum over chunks, in chunk order.
+__global__ void k_kpca_gram_reduce(const double* __restrict__ part, int nchunks, int l, int nb, double* G) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)l * l) return;
+    const int q = (int)(e / l), p = (int)(e - (int64_t)q * l);
+    const int bp = p / KG_B, bq = q / KG_B, pp = p - bp * KG_B, qq = q - bq * KG_B;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(((int64_t)c * nb + bp) * nb + bq) * (KG_B * KG_B) + pp * KG_B + qq];
+    G[e] = s;
+}
+
+// T[:, c0:c0+16] = Y W[:, c0:c0+16] (W column-major l x l, l <= 288).
+__global__ void __launch_bounds__(256) k_kpca_rowmul(const double* __restrict__ Y, int64_t n, int l,
+                                                     const double* __restrict__ W, double* __restrict__ T) {
+    __shared__ double ws[288 * 16];
+    const int c0 = blockIdx.y * 16;
+    for (int e = threadIdx.x; e < l * 16; e += 256) {
+        const int k = e / 16, c = e - k * 16;
+        ws[e] = c0 + c < l ? W[(int64_t)(c0 + c) * l + k] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    for (int k = 0; k < l; ++k) {
+        const double y = Y[(int64_t)k * n + i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = fma(y, ws[k * 16 + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (c0 + c < l) T[(int64_t)(c0 + c) * n + i] = acc[c];
+}
+
+size_t kpca_gram_part_doubles(int64_t n, int l) {
+    const int64_t nchunks = (n + KG_ROWS - 1) / KG_ROWS;
+    const int nb = (l + KG_B - 1) / KG_B;
+    return (size_t)nchunks * nb * nb * KG_B * KG_B;
+}
+
+hipError_t launch_kpca_gram(const double* A, const double* B, int64_t n, int l, double* part, double* G,
+                            hipStream_t stream) {
+    if (l < 1 || l > 288 || n < 1) return hipErrorInvalidValue;
+    const int nchunks = (int)((n + KG_ROWS - 1) / KG_ROWS);
+    const int nb = (l + KG_B - 1) / KG_B;
+    hipLaunchKernelGGL(k_kpca_gram_part, dim3(nchunks, nb, nb), dim3(256), 0, stream, A, B, n, l, part, nb);
+    hipLaunchKernelGGL(k_kpca_gram_reduce, dim3((int)(((int64_t)l * l + 255) / 256)), dim3(256), 0, stream,
+                       (const double*)part, nchunks, l, nb, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_kpca_rowmul(const double* Y, int64_t n, int l, const double* W, double* T, hipStream_t stream) {
+    if (l < 1 || l > 288 || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kpca_rowmul, dim3((int)((n + 255) / 256), (l + 15) / 16), dim3(256), 0, stream, Y, n, l, W,
+                       T);
+    return hipGetLastError();
+}
+
+}  // namespace gwk

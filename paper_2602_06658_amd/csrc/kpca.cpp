@@ -6,8 +6,10 @@
 // With rho_i = sum_k a_k c_ik and tau = sum_i a_i rho_i, Algorithm 4's kernel
 // is K = -(C - rho 1^T - 1 rho^T + tau 1 1^T) / 2, so for a block M,
 //   K M = -(C M)/2 + rho s^T / 2 + 1 (u - tau s)^T / 2,  s = M^T 1, u = M^T rho;
-// C M runs in k_kpca_cm, the rank-one terms, the orthonormalisation
-// (SVQB, twice) and the small Ritz problem in rocBLAS / rocSOLVER (FP64).
+// C M runs in k_kpca_cm, the tall-skinny Gram matrices and products in
+// k_kpca_gram / k_kpca_rowmul, the rank-one terms and the l x l problems
+// (SVQB orthonormalisation, twice; the Ritz eigensolve) in rocBLAS /
+// rocSOLVER, all in FP64.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -57,12 +59,10 @@ static Status apply_kernel(Ctx& c, rocblas_handle h, const KpcaPlan& k, const do
 // columns, which later give zero Ritz values.  The result lands in Y (T is
 // scratch of the same size; the two pointers are swapped).
 static Status orthonormalise(Ctx& c, rocblas_handle h, int64_t n64, int l, double*& Y, double*& T, double* G,
-                             double* W, double* sig, double* ework, double* scale, int* info) {
-    const int n = (int)n64;
-    const double one = 1.0, zero = 0.0;
+                             double* W, double* sig, double* ework, double* scale, int* info, double* gpart) {
     std::vector<double> hs(l), hscale(l);
     for (int pass = 0; pass < 2; ++pass) {
-        GW_RB(rocblas_dsyrk(h, rocblas_fill_upper, rocblas_operation_transpose, l, n, &one, Y, n, &zero, G, l));
+        GW_HIP(gwk::launch_kpca_gram(Y, Y, n64, l, gpart, G, c.stream));
         GW_RB(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, l, G, l, sig, ework, info));
         int hinfo = 0;
         GW_HIP(hipMemcpyAsync(hs.data(), sig, l * sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -74,8 +74,7 @@ static Status orthonormalise(Ctx& c, rocblas_handle h, int64_t n64, int l, doubl
         for (int q = 0; q < l; ++q) hscale[q] = hs[q] > 1e-24 * smax ? 1.0 / std::sqrt(hs[q]) : 0.0;
         GW_HIP(hipMemcpyAsync(scale, hscale.data(), l * sizeof(double), hipMemcpyHostToDevice, c.stream));
         GW_RB(rocblas_ddgmm(h, rocblas_side_right, l, l, G, l, scale, 1, W, l));
-        GW_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, l, l, &one, Y, n, W, l, &zero, T,
-                            n));
+        GW_HIP(gwk::launch_kpca_rowmul(Y, n64, l, W, T, c.stream));
         std::swap(Y, T);
         GW_HIP(hipStreamSynchronize(c.stream));  // hscale is read by the copy above
     }
@@ -99,6 +98,7 @@ Status kpca_full(Ctx& c, const float* x, int64_t n, int d, const float* w, doubl
     double* sig = c.ws.get_t<double>(tag + "kp.sig", l, &st);
     double* scale = c.ws.get_t<double>(tag + "kp.sc", l, &st);
     int* info = c.ws.get_t<int>(tag + "kp.info", 1, &st);
+    double* gpart = c.ws.get_t<double>(tag + "kp.gp", gwk::kpca_gram_part_doubles(n, l), &st);
     if (!st.good()) return st;
     if (!c.rocblas) {
         rocblas_handle hh;
@@ -122,20 +122,18 @@ Status kpca_full(Ctx& c, const float* x, int64_t n, int d, const float* w, doubl
     GW_HIP(gwk::launch_kpca_start(n, l, seed, Z, c.stream));
     GW_TRY(apply_kernel(c, h, k, Z, Y));
     for (int it = 0; it < n_iter; ++it) {
-        GW_TRY(orthonormalise(c, h, n, l, Y, Z, G, B, sig, ework, scale, info));
+        GW_TRY(orthonormalise(c, h, n, l, Y, Z, G, B, sig, ework, scale, info, gpart));
         GW_TRY(apply_kernel(c, h, k, Y, Z));
         std::swap(Y, Z);
     }
     // Rayleigh-Ritz on the final basis Q (= Y after orthonormalisation)
-    GW_TRY(orthonormalise(c, h, n, l, Y, Z, G, B, sig, ework, scale, info));
+    GW_TRY(orthonormalise(c, h, n, l, Y, Z, G, B, sig, ework, scale, info, gpart));
     GW_TRY(apply_kernel(c, h, k, Y, Z));
-    const double one = 1.0, zero = 0.0, half = 0.5;
-    GW_RB(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, l, l, (int)n, &one, Y, (int)n, Z,
-                        (int)n, &zero, G, l));
+    const double half = 0.5;
+    GW_HIP(gwk::launch_kpca_gram(Y, Z, n, l, gpart, G, c.stream));
     GW_RB(rocblas_dgeam(h, rocblas_operation_none, rocblas_operation_transpose, l, l, &half, G, l, &half, G, l, B, l));
     GW_RB(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, l, B, l, theta, ework, info));
-    GW_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, l, l, &one, Y, (int)n, B, l,
-                        &zero, Z, (int)n));
+    GW_HIP(gwk::launch_kpca_rowmul(Y, n, l, B, Z, c.stream));
     std::vector<double> hth(l);
     int hinfo = 0;
     GW_HIP(hipMemcpyAsync(hth.data(), theta, l * sizeof(double), hipMemcpyDeviceToHost, c.stream));
