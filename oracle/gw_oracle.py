@@ -28,6 +28,10 @@ Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
     sgw_divergence                                - Thm 4.3: zero between isometric
                                                     measures, non-negative; symmetric
                                                     in its two arguments
+    sgw_grad_positions                            - central differences of the
+                                                    converged divergence; zero at
+                                                    isometric measures (a minimum
+                                                    by Thm 4.3)
     landmark_lift, kernel_from_cost, kernel_pca   - full-rank exact embedding
     full_kpca_features                            - full-rank exact embedding for
                                                     p = 1/2, 1, 2; p = 2 equals
@@ -578,6 +582,35 @@ def sgw_divergence(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, inner_tol=N
     xx = one(a, X, a, X)
     yy = one(b, Y, b, Y)
     return {"sgw": xy - 0.5 * (xx + yy), "gw_xy": xy, "gw_xx": xx, "gw_yy": yy}
+
+
+def sgw_grad_positions(a, b, x, y, eps):
+    """Position gradient of the Sinkhorn-GW divergence (Section 4, "Entropic
+    Bias") for the squared Euclidean penalty, by the envelope theorem
+    (Appendix B.6) at solves converged at a fixed eps: the gradient of
+    GW_eps(alpha, beta) minus half that of GW_eps(alpha, alpha), in which x
+    is both the source and the target (the two envelope gradients summed);
+    the same for y.  Returns (grad_x, grad_y)."""
+    def parts(p, P, q, Q):
+        PP, QQ = centre(P, p), centre(Q, q)
+        gam, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps)
+        gs = chain_centre(grad_features(PP, QQ, p, q, pi, gam), p)
+        gt = chain_centre(grad_features_target(PP, QQ, p, q, pi, gam), q)
+        return gs, gt
+
+    gx, gy = parts(a, x, b, y)
+    sx, tx = parts(a, x, a, x)
+    sy, ty = parts(b, y, b, y)
+    return gx - 0.5 * (sx + tx), gy - 0.5 * (sy + ty)
+
+
+def sgw_value_converged(a, b, x, y, eps) -> float:
+    """SGW_eps with every EGW problem solved by cnt_gw_converged at eps."""
+    def one(p, P, q, Q):
+        PP, QQ = centre(P, p), centre(Q, q)
+        _, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps)
+        return egw_objective(PP, QQ, p, q, pi, eps)
+    return one(a, x, b, y) - 0.5 * (one(a, x, a, x) + one(b, y, b, y))
 
 
 def cnt_gw_converged(a, b, X, Y, eps, gamma0=None, tol=1e-13, max_outer=5000,
