@@ -224,10 +224,25 @@ def sgw_bench(args, gwm, torch, dev) -> dict:
     dt = time.perf_counter() - t0
     iters = prob.n_outer * prob.n_inner
     entries = float(prob.n * prob.m + prob.n * prob.n + prob.m * prob.m) * iters
+    # the divergence and its gradient with respect to the lifted features
+    X, Y = ctx.lift(0, x, a), ctx.lift(1, y, b)
+    fctx = gwm.Context()
+    fctx.set_penalty(2, "features")
+    grad_run = lambda: fctx.sgw_grad(X, a, Y, b, prob.eps_start, prob.eps_end, prob.n_outer,  # noqa: E731
+                                     prob.n_inner, precision=args.sgw_precision)
+    grad_run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gres = grad_run()
+    torch.cuda.synchronize()
+    gdt = time.perf_counter() - t0
     return {"workload": f"gmm3d N=M={prob.n}, |x-x'| lifted to D={prob.lifted_dim} (2048 landmarks), "
                         f"eps {prob.eps_start}->{prob.eps_end}, {prob.n_outer}x{prob.n_inner}, {args.sgw_precision}",
             "seconds": dt, "entries_per_s": entries / dt, "sgw": res["sgw"], "gw_xy": res["gw_xy"],
-            "gw_xx": res["gw_xx"], "gw_yy": res["gw_yy"], "marginal_err": res["marginal_err"]}
+            "gw_xx": res["gw_xx"], "gw_yy": res["gw_yy"], "marginal_err": res["marginal_err"],
+            "with_feature_gradient": {"seconds": gdt, "sgw": gres["sgw"],
+                                      "grad_x_norm": float(gres["grad_x"].norm()),
+                                      "grad_y_norm": float(gres["grad_y"].norm())}}
 
 
 def adaptive_bench(args, gwm, torch, dev) -> dict:

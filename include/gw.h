@@ -210,6 +210,20 @@ gw_status gw_sgw(gw_ctx* ctx,
                  const float* y, int64_t m, int dy, const float* b,
                  const gw_params* params, gw_sgw_result* out);
 
+/* Position gradient of the Sinkhorn-GW divergence (Section 4; envelope
+   gradients of Appendix B.6): the three solves of gw_sgw on the raw points,
+   then grad_x = dGW(x, y)/dx - (dGW(x, x)/dx_source + dGW(x, x)/dx_target) / 2
+   and the same for y (device, caller allocated, n x dx and m x dy).  The
+   envelope gradient is exact at converged solves.  Both sides must use the
+   same GW_PEN_SQEUCLID or GW_PEN_FEATURES penalty (GW_EUNSUPPORTED
+   otherwise); weight gradients are not provided.  Other inputs, outputs and
+   errors as gw_sgw. */
+gw_status gw_sgw_grad(gw_ctx* ctx,
+                      const float* x, int64_t n, int dx, const float* a,
+                      const float* y, int64_t m, int dy, const float* b,
+                      const gw_params* params, gw_sgw_result* out,
+                      float* grad_x, float* grad_y);
+
 /* Full-N kernel PCA (Appendix B, "Kernel PCA"; the paper's KeOps + eigsh
    route for all points): features X (n x D, device, row-major, caller
    allocated) with X_i = V_i sqrt(Lambda) for the D largest eigenpairs of

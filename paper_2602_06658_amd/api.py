@@ -228,6 +228,22 @@ class Context:
         out["info"] = {k: getattr(info, k) for k, _ in L.GwMsgwInfo._fields_}
         return out
 
+    def sgw_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
+                 precision="fp32", mode="auto") -> dict:
+        """The divergence (gw_sgw fields) and its position gradients
+        (gw_sgw_grad) under the same squared-norm or feature penalty."""
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode, False, 0.0)
+        r = L.GwSgwResult()
+        gx, gy = torch.empty_like(x), torch.empty_like(y)
+        self._check(self.lib.gw_sgw_grad(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
+                                         ctypes.byref(prm), ctypes.byref(r), _ptr(gx), _ptr(gy)))
+        out = {k: getattr(r, k) for k, _ in L.GwSgwResult._fields_}
+        out.update({"grad_x": gx, "grad_y": gy})
+        return out
+
     def loss_and_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                       precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, want=("x", "a", "y", "b")):
         x, a, y, b = self._prep(x, a, y, b)

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <new>
 
+#include "gw_grad.h"
 #include "runtime.h"
 
 using gwr::Ctx;
@@ -185,6 +186,53 @@ gw_status gw_sgw(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a,
     out->marginal_err = std::max(rxy.marginal_err, std::max(rxx.marginal_err, ryy.marginal_err));
     out->dim_x = D;
     out->dim_y = E;
+    return ret(ctx, Status::ok());
+}
+
+gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
+                      int dy, const float* b, const gw_params* params, gw_sgw_result* out, float* grad_x,
+                      float* grad_y) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (!out || !grad_x || !grad_y) return ret(ctx, gwr::fail(GW_EINVAL, "result or gradient is NULL"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = gwr::validate_inputs(ctx->c, x, n, dx, a, y, m, dy, b, params, "sgw.");
+    if (!st.good()) return ret(ctx, st);
+    if (params->use_init_potentials) return ret(ctx, gwr::fail(GW_EINVAL, "the divergence starts from zero potentials"));
+    gwr::Ctx& c = ctx->c;
+    const int kind = c.side[0].kind;
+    if (c.side[1].kind != kind || (kind != GW_PEN_SQEUCLID && kind != GW_PEN_FEATURES))
+        return ret(ctx, gwr::fail(GW_EUNSUPPORTED,
+                                  "the divergence's gradient needs the same squared-norm or feature penalty on both sides"));
+    float* gxs = c.ws.get_t<float>("sgw.gxs", (size_t)n * dx, &st);
+    float* gxt = c.ws.get_t<float>("sgw.gxt", (size_t)n * dx, &st);
+    float* gys = c.ws.get_t<float>("sgw.gys", (size_t)m * dy, &st);
+    float* gyt = c.ws.get_t<float>("sgw.gyt", (size_t)m * dy, &st);
+    if (!st.good()) return ret(ctx, st);
+    auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
+                   const float* wq, gw_result& r, float* gP, float* gQ) -> Status {
+        gwr::Solve solve(c, "s.");
+        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, kind, kind, c.stream));
+        while (!solve.done()) GW_TRY(solve.outer_step());
+        GW_TRY(solve.finish(&r));
+        return solve.gradients(gP, nullptr, gQ, nullptr);
+    };
+    gw_result rxy{}, rxx{}, ryy{};
+    st = run(x, n, dx, a, y, m, dy, b, rxy, grad_x, grad_y);
+    if (st.good()) st = run(x, n, dx, a, x, n, dx, a, rxx, gxs, gxt);
+    if (st.good()) st = run(y, m, dy, b, y, m, dy, b, ryy, gys, gyt);
+    if (!st.good()) return ret(ctx, st);
+    if (gwk::launch_sub_half_sum(grad_x, gxs, gxt, n * dx, c.stream) != hipSuccess ||
+        gwk::launch_sub_half_sum(grad_y, gys, gyt, m * dy, c.stream) != hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+        return ret(ctx, gwr::fail(GW_EDEVICE, "divergence gradient"));
+    out->gw_xy = rxy.egw_objective;
+    out->gw_xx = rxx.egw_objective;
+    out->gw_yy = ryy.egw_objective;
+    out->sgw = rxy.egw_objective - 0.5 * (rxx.egw_objective + ryy.egw_objective);
+    out->marginal_err = std::max(rxy.marginal_err, std::max(rxx.marginal_err, ryy.marginal_err));
+    out->dim_x = rxy.dim_x;
+    out->dim_y = rxy.dim_y;
     return ret(ctx, Status::ok());
 }
 

@@ -52,4 +52,7 @@ hipError_t launch_grad_rows(const GradSide& s, double* G, double* gw, double* pa
 hipError_t launch_grad_apply(const double* G, const double* gw, int64_t rows, int d, const float* w, double wscale,
                              const double* sums, float* gfeat, float* gweight, hipStream_t stream);
 
+// out_i -= (p_i + q_i) / 2, count floats.
+hipError_t launch_sub_half_sum(float* out, const float* p, const float* q, int64_t count, hipStream_t stream);
+
 }  // namespace gwk

@@ -166,4 +166,16 @@ hipError_t launch_grad_apply(const double* G, const double* gw, int64_t rows, in
     return hipGetLastError();
 }
 
+// out_i -= (p_i + q_i) / 2 (the divergence's self terms, Section 4).
+__global__ void k_sub_half_sum(float* out, const float* __restrict__ p, const float* __restrict__ q, int64_t count) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < count) out[i] -= 0.5f * (p[i] + q[i]);
+}
+
+hipError_t launch_sub_half_sum(float* out, const float* p, const float* q, int64_t count, hipStream_t stream) {
+    if (count < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_sub_half_sum, dim3((int)((count + 255) / 256)), dim3(256), 0, stream, out, p, q, count);
+    return hipGetLastError();
+}
+
 }  // namespace gwk
