@@ -28,6 +28,8 @@ Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
     sgw_divergence                                - Thm 4.3: zero between isometric
                                                     measures, non-negative; symmetric
                                                     in its two arguments
+    sgw_barycenter                                - descent, first-order decrease
+                                                    matching the step's scaling
     sgw_grad_positions                            - central differences of the
                                                     converged divergence; zero at
                                                     isometric measures (a minimum
@@ -584,16 +586,17 @@ def sgw_divergence(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, inner_tol=N
     return {"sgw": xy - 0.5 * (xx + yy), "gw_xy": xy, "gw_xx": xx, "gw_yy": yy}
 
 
-def sgw_grad_positions(a, b, x, y, eps):
+def sgw_grad_positions(a, b, x, y, eps, tol=1e-13):
     """Position gradient of the Sinkhorn-GW divergence (Section 4, "Entropic
     Bias") for the squared Euclidean penalty, by the envelope theorem
     (Appendix B.6) at solves converged at a fixed eps: the gradient of
     GW_eps(alpha, beta) minus half that of GW_eps(alpha, alpha), in which x
     is both the source and the target (the two envelope gradients summed);
-    the same for y.  Returns (grad_x, grad_y)."""
+    the same for y.  tol: the outer and inner tolerances of the converged
+    solves (tol and tol / 10).  Returns (grad_x, grad_y)."""
     def parts(p, P, q, Q):
         PP, QQ = centre(P, p), centre(Q, q)
-        gam, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps)
+        gam, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps, tol=tol, sink_tol=tol / 10)
         gs = chain_centre(grad_features(PP, QQ, p, q, pi, gam), p)
         gt = chain_centre(grad_features_target(PP, QQ, p, q, pi, gam), q)
         return gs, gt
@@ -604,13 +607,34 @@ def sgw_grad_positions(a, b, x, y, eps):
     return gx - 0.5 * (sx + tx), gy - 0.5 * (sy + ty)
 
 
-def sgw_value_converged(a, b, x, y, eps) -> float:
+def sgw_value_converged(a, b, x, y, eps, tol=1e-13) -> float:
     """SGW_eps with every EGW problem solved by cnt_gw_converged at eps."""
     def one(p, P, q, Q):
         PP, QQ = centre(P, p), centre(Q, q)
-        _, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps)
+        _, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps, tol=tol, sink_tol=tol / 10)
         return egw_objective(PP, QQ, p, q, pi, eps)
     return one(a, x, b, y) - 0.5 * (one(a, x, a, x) + one(b, y, b, y))
+
+
+def sgw_barycenter(a, b, x, y, z0, w, lam, step, n_steps, eps, tol=1e-13):
+    """GW barycentre flow (Section 6, "GW Barycenters"): gradient descent on
+    the points z of gamma_z = sum_i w_i delta_{z_i} for
+    (1 - lam) SGW_eps(gamma_z, alpha) + lam SGW_eps(gamma_z, beta), squared
+    Euclidean penalty, converged solves; each point moves by -step / w_i
+    times its gradient (the gradient per unit of mass).  Returns z after
+    n_steps and the objective before each step and after the last."""
+    z = np.array(z0, np.float64)
+    w = np.asarray(w, np.float64)
+    obj = []
+    for s in range(n_steps + 1):
+        obj.append((1 - lam) * sgw_value_converged(w, a, z, x, eps, tol)
+                   + lam * sgw_value_converged(w, b, z, y, eps, tol))
+        if s == n_steps:
+            break
+        gzx, _ = sgw_grad_positions(w, a, z, x, eps, tol)
+        gzy, _ = sgw_grad_positions(w, b, z, y, eps, tol)
+        z = z - step / w[:, None] * ((1 - lam) * gzx + lam * gzy)
+    return z, obj
 
 
 def cnt_gw_converged(a, b, X, Y, eps, gamma0=None, tol=1e-13, max_outer=5000,
