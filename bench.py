@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--sgw-only", action="store_true",
                     help="measure only the Sinkhorn-GW divergence (three solves) on the 20k workload")
     ap.add_argument("--sgw-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--barycenter", action="store_true",
+                    help="GW barycentre flow on two 3,000-point clouds")
     ap.add_argument("--adaptive", action="store_true",
                     help="fixed against adaptive Sinkhorn counts on the 20,000-point workload")
     ap.add_argument("--kpca", action="store_true",
@@ -284,6 +286,35 @@ def adaptive_bench(args, gwm, torch, dev) -> dict:
     return out
 
 
+def barycenter_bench(args, gwm, torch, dev) -> dict:
+    """GW barycentre flow at the paper's size (Section 6: 3,000 points per
+    shape in 3-D, uniform weights): alpha and beta two different 8-component
+    mixtures, z started at a third sample, lam = 0.5, 10 steps; each step is
+    three Algorithm 1 solves (z, alpha), (z, beta), (z, z) of 20 x 50 FP32
+    iterations at eps 0.1 plus their envelope gradients."""
+    from workloads import gmm_points
+
+    n = 3000
+    t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
+    rng = np.random.default_rng(9100)
+    x = t(gmm_points(rng, n, rng.uniform(-1, 1, (8, 3)), 0.1))
+    y = t(gmm_points(rng, n, rng.uniform(-1, 1, (8, 3)) * np.array([1.0, 0.5, 0.25]), 0.1))
+    z0 = t(gmm_points(rng, n, rng.uniform(-1, 1, (8, 3)), 0.2))
+    w = t(np.full(n, 1.0 / n))
+    ctx = gwm.Context()
+    out = {"workload": f"N={n} points per cloud in 3-D, squared-norm penalty, lam 0.5, 10 steps, eps 0.1, "
+                       "20x50 fp32 per solve"}
+    for step in (0.002, 0.01):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, obj = ctx.sgw_barycenter(x, w, y, w, z0, w, 0.5, step, 10, 0.1, 0.1, 20, 50)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"step_{step}"] = {"seconds": dt, "seconds_per_step": dt / 10, "objective": obj}
+        print(f"barycentre: step {step} done", file=sys.stderr, flush=True)
+    return out
+
+
 def multiseed_bench(args, gwm, torch, dev) -> dict:
     """One pair shaped like the serving workload (5,000 points per side in
     3-D, one 8-component mixture, the target under a rigid motion, |x - x'|
@@ -448,6 +479,9 @@ def main():
         return
     if args.adaptive:
         print(json.dumps({"adaptive": adaptive_bench(args, gwm, torch, dev)}), flush=True)
+        return
+    if args.barycenter:
+        print(json.dumps({"barycenter": barycenter_bench(args, gwm, torch, dev)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(args, gwm, torch, dev)}), flush=True)

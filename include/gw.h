@@ -224,6 +224,25 @@ gw_status gw_sgw_grad(gw_ctx* ctx,
                       const gw_params* params, gw_sgw_result* out,
                       float* grad_x, float* grad_y);
 
+/* GW barycentre flow (Section 6, "GW Barycenters"): gradient descent on the
+   points z (k x d, device, in/out) of gamma_z = sum_i w_i delta_{z_i} (w:
+   k device weights, > 0, sum 1) for the objective
+   (1 - lambda) SGW_eps(gamma_z, alpha) + lambda SGW_eps(gamma_z, beta), with
+   alpha = (x, a) (n x d) and beta = (y, b) (m x d) on the device.  Each of
+   the n_steps steps runs Algorithm 1 on (z, x), (z, y) and (z, z) with params,
+   takes the divergence's position gradient (gw_sgw_grad) and moves
+   z_i -= step / w_i * gradient_i; GW_eps(alpha, alpha) and GW_eps(beta, beta)
+   are solved once.  objective (host, n_steps + 1 values, nullable) receives
+   the objective before each step and after the last.  Same penalty
+   restriction and errors as gw_sgw_grad; GW_EINVAL for lambda outside
+   [0, 1], step < 0 or n_steps outside [0, 100000]. */
+gw_status gw_sgw_barycenter(gw_ctx* ctx,
+                            const float* x, int64_t n, const float* a,
+                            const float* y, int64_t m, const float* b, int d,
+                            float* z, int64_t k, const float* w,
+                            double lambda, double step, int n_steps,
+                            const gw_params* params, double* objective);
+
 /* Full-N kernel PCA (Appendix B, "Kernel PCA"; the paper's KeOps + eigsh
    route for all points): features X (n x D, device, row-major, caller
    allocated) with X_i = V_i sqrt(Lambda) for the D largest eigenpairs of

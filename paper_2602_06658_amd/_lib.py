@@ -152,6 +152,11 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                    ctypes.POINTER(GwParams), ctypes.POINTER(GwSgwResult), ctypes.c_void_p,
                                    ctypes.c_void_p]),
+    "gw_sgw_barycenter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.POINTER(GwParams),
+                                         ctypes.POINTER(ctypes.c_double)]),
     "gw_kpca_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),

@@ -244,6 +244,20 @@ class Context:
         out.update({"grad_x": gx, "grad_y": gy})
         return out
 
+    def sgw_barycenter(self, x, a, y, b, z0, w, lam: float, step: float, n_steps: int, eps_start, eps_end=None,
+                       n_outer=20, n_inner=50, symmetric=True, precision="fp32", mode="auto"):
+        """GW barycentre flow (gw_sgw_barycenter): returns the moved points z
+        and the objective before each step and after the last."""
+        x, a, y, b = self._prep(x, a, y, b)
+        z = _dev_f32(z0, "z0").clone()
+        w = _dev_f32(w, "w")
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode, False, 0.0)
+        obj = (ctypes.c_double * (n_steps + 1))()
+        self._check(self.lib.gw_sgw_barycenter(self.h, _ptr(x), x.shape[0], _ptr(a), _ptr(y), y.shape[0], _ptr(b),
+                                               x.shape[1], _ptr(z), z.shape[0], _ptr(w), float(lam), float(step),
+                                               int(n_steps), ctypes.byref(prm), obj))
+        return z, [float(v) for v in obj]
+
     def loss_and_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                       precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, want=("x", "a", "y", "b")):
         x, a, y, b = self._prep(x, a, y, b)

@@ -1,5 +1,6 @@
 // extern "C" entry points of libgwmi.so (declared in include/gw.h).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -234,6 +235,63 @@ gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const floa
     out->dim_x = rxy.dim_x;
     out->dim_y = rxy.dim_y;
     return ret(ctx, Status::ok());
+}
+
+gw_status gw_sgw_barycenter(gw_ctx* ctx, const float* x, int64_t n, const float* a, const float* y, int64_t m,
+                            const float* b, int d, float* z, int64_t k, const float* w, double lambda, double step,
+                            int n_steps, const gw_params* params, double* objective) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (!z || !w) return ret(ctx, gwr::fail(GW_EINVAL, "z or w is NULL"));
+    if (k < 1 || k > ((int64_t)1 << 30)) return ret(ctx, gwr::fail(GW_EINVAL, "k out of range"));
+    if (!(lambda >= 0.0 && lambda <= 1.0)) return ret(ctx, gwr::fail(GW_EINVAL, "lambda must be in [0, 1]"));
+    if (!(step >= 0.0) || !std::isfinite(step)) return ret(ctx, gwr::fail(GW_EINVAL, "step must be finite and >= 0"));
+    if (n_steps < 0 || n_steps > 100000) return ret(ctx, gwr::fail(GW_EINVAL, "n_steps must be in [0, 100000]"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = gwr::validate_inputs(ctx->c, x, n, d, a, y, m, d, b, params, "bc.");
+    if (st.good()) st = gwr::validate_inputs(ctx->c, z, k, d, w, x, n, d, a, params, "bc.");
+    if (!st.good()) return ret(ctx, st);
+    if (params->use_init_potentials) return ret(ctx, gwr::fail(GW_EINVAL, "the divergence starts from zero potentials"));
+    gwr::Ctx& c = ctx->c;
+    const int kind = c.side[0].kind;
+    if (c.side[1].kind != kind || (kind != GW_PEN_SQEUCLID && kind != GW_PEN_FEATURES))
+        return ret(ctx, gwr::fail(GW_EUNSUPPORTED,
+                                  "the barycentre flow needs the same squared-norm or feature penalty on both sides"));
+    float* g1 = c.ws.get_t<float>("bc.g1", (size_t)k * d, &st);
+    float* g2 = c.ws.get_t<float>("bc.g2", (size_t)k * d, &st);
+    float* gs = c.ws.get_t<float>("bc.gs", (size_t)k * d, &st);
+    float* gt = c.ws.get_t<float>("bc.gt", (size_t)k * d, &st);
+    if (!st.good()) return ret(ctx, st);
+    auto run = [&](const float* P, int64_t np, const float* wp, const float* Q, int64_t nq, const float* wq,
+                   double* egw, float* gP, float* gQ) -> Status {
+        gwr::Solve solve(c, "s.");
+        GW_TRY(solve.setup(P, np, d, wp, Q, nq, d, wq, *params, nullptr, nullptr, nullptr, kind, kind, c.stream));
+        while (!solve.done()) GW_TRY(solve.outer_step());
+        gw_result r{};
+        GW_TRY(solve.finish(&r));
+        *egw = r.egw_objective;
+        if (gP || gQ) GW_TRY(solve.gradients(gP, nullptr, gQ, nullptr));
+        return Status::ok();
+    };
+    // GW(alpha, alpha) and GW(beta, beta) do not move with z
+    double eaa = 0.0, ebb = 0.0;
+    st = run(x, n, a, x, n, a, &eaa, nullptr, nullptr);
+    if (st.good()) st = run(y, m, b, y, m, b, &ebb, nullptr, nullptr);
+    for (int s = 0; st.good() && s <= n_steps; ++s) {
+        const bool last = s == n_steps;
+        double ezx = 0.0, ezy = 0.0, ezz = 0.0;
+        st = run(z, k, w, x, n, a, &ezx, last ? nullptr : g1, nullptr);
+        if (st.good()) st = run(z, k, w, y, m, b, &ezy, last ? nullptr : g2, nullptr);
+        if (st.good()) st = run(z, k, w, z, k, w, &ezz, last ? nullptr : gs, last ? nullptr : gt);
+        if (!st.good()) break;
+        if (objective)
+            objective[s] = (1.0 - lambda) * (ezx - 0.5 * (ezz + eaa)) + lambda * (ezy - 0.5 * (ezz + ebb));
+        if (!last && gwk::launch_bary_step(z, k, d, w, g1, g2, gs, gt, (float)lambda, (float)step, c.stream) !=
+                         hipSuccess)
+            st = gwr::fail(GW_EDEVICE, "barycentre step");
+    }
+    if (st.good() && hipStreamSynchronize(c.stream) != hipSuccess) st = gwr::fail(GW_EDEVICE, "barycentre flow");
+    return ret(ctx, st);
 }
 
 gw_status gw_set_profiling(gw_ctx* ctx, int enable) {

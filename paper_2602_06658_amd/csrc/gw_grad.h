@@ -55,4 +55,8 @@ hipError_t launch_grad_apply(const double* G, const double* gw, int64_t rows, in
 // out_i -= (p_i + q_i) / 2, count floats.
 hipError_t launch_sub_half_sum(float* out, const float* p, const float* q, int64_t count, hipStream_t stream);
 
+// z_i -= step / w_i ((1 - lam) g1_i + lam g2_i - (gs_i + gt_i) / 2), k x d floats.
+hipError_t launch_bary_step(float* z, int64_t k, int d, const float* w, const float* g1, const float* g2,
+                            const float* gs, const float* gt, float lam, float step, hipStream_t stream);
+
 }  // namespace gwk

@@ -178,4 +178,25 @@ hipError_t launch_sub_half_sum(float* out, const float* p, const float* q, int64
     return hipGetLastError();
 }
 
+// One descent step of the barycentre flow: z_i -= step / w_i * ((1 - lam) g1_i
+// + lam g2_i - (gs_i + gt_i) / 2), the gradient of (1 - lam) SGW(z, alpha) +
+// lam SGW(z, beta) scaled by the inverse point weights.
+__global__ void k_bary_step(float* z, int64_t k, int d, const float* __restrict__ w, const float* __restrict__ g1,
+                            const float* __restrict__ g2, const float* __restrict__ gs, const float* __restrict__ gt,
+                            float lam, float step) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= k * d) return;
+    const float g = (1.f - lam) * g1[e] + lam * g2[e] - 0.5f * (gs[e] + gt[e]);
+    z[e] -= step / w[e / d] * g;
+}
+
+hipError_t launch_bary_step(float* z, int64_t k, int d, const float* w, const float* g1, const float* g2,
+                            const float* gs, const float* gt, float lam, float step, hipStream_t stream) {
+    const int64_t count = k * d;
+    if (count < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_bary_step, dim3((int)((count + 255) / 256)), dim3(256), 0, stream, z, k, d, w, g1, g2, gs,
+                       gt, lam, step);
+    return hipGetLastError();
+}
+
 }  // namespace gwk
