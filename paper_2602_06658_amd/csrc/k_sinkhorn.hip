@@ -587,6 +587,15 @@ Geometry pass_geometry(int prec, int d, int64_t n, int64_t m, int multiplier) {
         g.rows_per_group = WAVES * rows_per_wave_tiles(prec, d) * 32;
     }
     g.bc_chunks = n_chunks_c < 32 ? n_chunks_c : 32;
+    if (g.path == 1) {
+        // small problems on the VALU path: narrower column tiles (even chunk
+        // counts, at least 2) until the grid has ~1024 workgroups, so that a
+        // few thousand rows still fill the 256 CUs
+        const int64_t nmr_min = (g.n_pad + g.rows_per_group - 1) / g.rows_per_group;
+        while (g.bc_chunks > 2 && (g.bc_chunks & 1) == 0 &&
+               nmr_min * ((n_chunks_c + g.bc_chunks - 1) / g.bc_chunks) < 1024)
+            g.bc_chunks >>= 1;
+    }
     g.n_mt_c = (n_chunks_c + g.bc_chunks - 1) / g.bc_chunks;
     // as many row groups per macro tile as keeps >= ~2048 workgroups
     const int target = 2048 * (multiplier > 0 ? multiplier : 1);
