@@ -463,7 +463,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+              "not built (the row-sharded design is described with the library)", file=sys.stderr)
         sys.exit(2)
     import torch
 

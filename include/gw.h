@@ -47,7 +47,7 @@ typedef enum {
     GW_EDEVICE = 3,       /* HIP runtime error */
     GW_ENUMERIC = 4,      /* non-finite value detected in the iteration */
     GW_ESTATE = 5,        /* call not valid in the context's current state */
-    GW_EUNSUPPORTED = 6,  /* valid request this build does not implement */
+    GW_EUNSUPPORTED = 6,  /* valid request the library does not implement */
     GW_EBUSY = 7,         /* serving: result not ready yet */
     GW_ECANCELLED = 8     /* serving: request was cancelled */
 } gw_status;
