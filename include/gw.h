@@ -105,11 +105,16 @@ typedef struct {
                                   n_inner is the first step's count, and it
                                   doubles after a step whose coupling has a
                                   larger EGW objective (at that step's eps)
-                                  than the previous coupling, by more than
-                                  1e-6 max(|EGW|, C), C the constant of Lemma
-                                  C.1 (the previous coupling of step
-                                  0 is a x b when gamma0 is NULL, none
-                                  otherwise); capped at 64 x n_inner.  Each
+                                  than the previous coupling (the previous
+                                  coupling of step 0 is a x b when gamma0 is
+                                  NULL, none otherwise).  Two implementation
+                                  limits depart from the paper's rule, which
+                                  doubles on any increase without bound: an
+                                  increase counts only above 1e-6 max(|EGW|,
+                                  C), C the constant of Lemma C.1, since the
+                                  objective is evaluated from single-precision
+                                  passes; and the count is capped at
+                                  64 x n_inner.  Each
                                   outer step then runs the FP64 check (one
                                   extra N x M evaluation and a readback).
                                   gw_solve only (the server rejects it).

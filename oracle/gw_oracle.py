@@ -261,6 +261,12 @@ def kl_divergence(pi, a, b) -> float:
 # --------------------------------------------------------------------------
 
 
+# Algorithm 6 doubles the count when the EGW objective increases.  An
+# increase is taken to be one above the float64 rounding of the two values
+# compared (relative to the scale of the terms they are differences of).
+ADAPTIVE_TIE = 1e-12
+
+
 def eps_schedule(eps_start: float, eps_end: float, n_outer: int) -> np.ndarray:
     """Outer temperature schedule.  The paper fixes eps; an annealed
     schedule is read as geometric, eps_t = eps_0 (eps_end/eps_0)^(t/(T-1))."""
@@ -286,6 +292,7 @@ class GWResult:
     history: list = field(default_factory=list)
     n_inner_final: int = 0   # Sinkhorn count of the last outer step
     doublings: int = 0       # adaptive counts: doublings made
+    adaptive_log: list = field(default_factory=list)   # (t, e_new, e_old, scale, doubled)
 
 
 def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
@@ -309,10 +316,14 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     "Adaptive Sinkhorn Iterations", with the lifted squared-norm loss as the
     base cost): after each outer step the EGW objective L_lift + eps KL of
     the new plan is compared with that of the previous plan at the same
-    eps; when it is larger by more than 1e-6 max(|EGW|, C) (C the constant
-    of Lemma C.1, the scale of the terms the loss is a difference of) the
-    count doubles, up to 64 n_inner.  The previous plan of step 0 is a x b when gamma0 is
-    None; with a given gamma0 the first comparison is after step 1."""
+    eps, and the count doubles when the new value is larger.  "Larger" is
+    read as larger by more than the float64 rounding of the comparison,
+    1e-12 max(|EGW|, C) (C the constant of Lemma C.1, the scale of the terms
+    the loss is a difference of), so that an exact tie never fires; there
+    is no cap.  The previous plan of step 0 is a x b when gamma0 is None;
+    with a given gamma0 the first comparison is after step 1.  Each
+    comparison is recorded in GWResult.adaptive_log as (t, e_new, e_old,
+    scale, doubled)."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     X = np.asarray(X, np.float64)
@@ -326,6 +337,7 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     pi = None
     eps_list = list(eps_schedule(eps_start, eps_end, n_outer))
     n_in, doublings = int(n_inner), 0
+    adaptive_log = []
     prev = None
     c_scale = constant_c(X, Y, a, b) if adaptive else 0.0
     if adaptive and gamma0 is None:
@@ -355,11 +367,14 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
             cur = (lifted_loss(X, Y, a, b, pi), kl_divergence(pi, a, b))
             if prev is not None:
                 e_new, e_old = cur[0] + eps * cur[1], prev[0] + eps * prev[1]
-                if e_new - e_old > 1e-6 * max(abs(e_old), c_scale) and n_in < 64 * n_inner:
-                    n_in = min(2 * n_in, 64 * n_inner)
+                scale = max(abs(e_old), c_scale)
+                doubled = e_new - e_old > ADAPTIVE_TIE * scale
+                if doubled:
+                    n_in *= 2
                     doublings += 1
+                adaptive_log.append((t, e_new, e_old, scale, doubled))
             prev = cur
-    return GWResult(f, g, gamma, gamma_prev, pi, float(eps_list[-1]), hist, n_in, doublings)
+    return GWResult(f, g, gamma, gamma_prev, pi, float(eps_list[-1]), hist, n_in, doublings, adaptive_log)
 
 
 # --------------------------------------------------------------------------

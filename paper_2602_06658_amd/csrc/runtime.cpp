@@ -587,10 +587,14 @@ Status Solve::outer_step() {
 
 // Algorithm 6 (adaptive Sinkhorn iterations) for CNT-GW: the EGW objective
 // L_lift + eps KL of the new coupling against that of the previous one, both
-// at this step's eps; a value larger by more than 1e-6 max(|EGW|, C) (C of
-// Lemma C.1, the scale of the terms L_lift is a difference of) means the
-// inner solve was too short, and the count doubles.  L_lift = C - 8 |Gamma_{t+1}|^2 - 4 sum pi n m comes from
-// the covariance pass, KL from the FP64 check of the same coupling.
+// at this step's eps; an increase means the inner solve was too short, and
+// the count doubles.  The paper doubles on any increase.  Here an increase
+// counts only above 1e-6 max(|EGW|, C) (C of Lemma C.1, the scale of the
+// terms L_lift is a difference of): L_lift comes from single-precision
+// passes, and smaller changes are within their rounding.  This tolerance,
+// and the cap of 64 n_inner, are implementation limits, not the paper's
+// rule.  L_lift = C - 8 |Gamma_{t+1}|^2 - 4 sum pi n m comes from the
+// covariance pass, KL from the FP64 check of the same coupling.
 Status Solve::adaptive_step() {
     GW_TRY(enqueue_check());
     const size_t nmx = 2 + (size_t)D_ * D_ + D_, nmy = 2 + (size_t)E_ * E_ + E_;

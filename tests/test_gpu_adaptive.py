@@ -1,10 +1,15 @@
 """Algorithm 6's adaptive Sinkhorn counts on the GPU (gw_params.adaptive_inner)
-against the oracle's CNT-GW with the same rule: the same doublings, the same
-final count, the EGW objective within the FP32 loss tolerance 1e-5.  The
-cases are chosen so that no change of the objective between outer steps
-lies within a factor 2.5 of the rule's threshold 1e-6 max(|EGW|, C), so
-that single-precision rounding cannot flip a decision; the server rejects
-the mode."""
+against the oracle's CNT-GW with the paper's rule (double on any increase of
+the EGW objective beyond float64 rounding): the same doublings, the same
+final count, the EGW objective within the FP32 loss tolerance 1e-5.
+
+The GPU doubles only on increases above 1e-6 max(|EGW|, C), its
+single-precision tolerance.  The cases are chosen so that the two rules take
+the same decisions: every increase of the objective between outer steps in
+the oracle's run is above 2.5e-6 of the scale, and no count reaches the
+GPU's cap of 64 n_inner (the oracle records each comparison, and the test
+checks this before comparing).  A case where the rules differ is pinned on
+the CPU (test_oracle_adaptive.py).  The server rejects the mode."""
 import numpy as np
 import pytest
 import torch
@@ -29,7 +34,7 @@ def _case(seed, n, m, d):
 
 
 @pytest.mark.parametrize("seed,n,m,d,eps,T,nin", [(5, 300, 260, 2, 0.3, 40, 1), (6, 300, 260, 2, 0.1, 30, 2),
-                                                  (7, 400, 350, 16, 0.5, 30, 2)])
+                                                  (11, 400, 350, 16, 0.5, 20, 2)])
 def test_adaptive_counts_match_oracle(gw, seed, n, m, d, eps, T, nin):
     x, a, y, b = _case(seed, n, m, d)
     ctx = gw.Context()
@@ -39,6 +44,9 @@ def test_adaptive_counts_match_oracle(gw, seed, n, m, d, eps, T, nin):
     res = ctx.solve(dev(x), dev(a), dev(y), dev(b), eps, eps, T, nin, precision="fp32", adaptive_inner=True)
     X, Y = O.centre(x, a), O.centre(y, b)
     ref = O.cnt_gw(a, b, X, Y, eps, eps, T, nin, adaptive=True)
+    ratios = [(e1 - e0) / sc for (_, e1, e0, sc, _) in ref.adaptive_log]
+    assert not [q for q in ratios if O.ADAPTIVE_TIE < q <= 2.5e-6], ratios
+    assert ref.n_inner_final <= 64 * nin
     egw = O.egw_objective(X, Y, a, b, ref.pi, ref.eps)
     print(res["inner_doublings"], ref.doublings, res["n_inner_final"], ref.n_inner_final, res["egw_objective"], egw)
     assert res["inner_doublings"] == ref.doublings and res["n_inner_final"] == ref.n_inner_final
