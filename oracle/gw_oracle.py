@@ -18,9 +18,11 @@ design notes; each function states the passage it follows.
 
 Parity status per function (what pins it, in ``tests/test_oracle_*.py``):
     centre, lifted_loss, constant_c, quartic_loss  - brute force / closed form
-    sinkhorn                                      - unique EOT optimum, textbook
+    sinkhorn (NumPy and C loops)                  - unique EOT optimum, textbook
                                                     scaling iteration, separable
-                                                    costs, N = 1
+                                                    costs, N = 1; the C loop
+                                                    (sinkhorn.c) also equals the
+                                                    NumPy loop to float64 rounding
     cnt_gw                                        - Entropic-GW and Kernel-GW
                                                     agreement, permutation
                                                     enumeration, rigid motion,
@@ -221,12 +223,61 @@ def softmin_cols(a: np.ndarray, f: np.ndarray, c: np.ndarray, eps: float) -> np.
     return -eps * lse(np.log(a)[:, None] + (f[:, None] - c) / eps, axis=0)
 
 
-def sinkhorn(a, b, c, eps, n_iter, f0=None, g0=None, symmetric=True):
+_CLIB = None
+
+
+def _c_sinkhorn_lib():
+    """The oracle's compiled Sinkhorn loop (sinkhorn.c), built with gcc on
+    first use if it is missing."""
+    global _CLIB
+    if _CLIB is None:
+        import ctypes
+        import os
+
+        from . import build_c
+        if not os.path.exists(build_c.OUT):
+            build_c.build()
+        lib = ctypes.CDLL(build_c.OUT)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_sinkhorn.argtypes = [dp, dp, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.oracle_sinkhorn.restype = ctypes.c_int
+        _CLIB = lib
+    return _CLIB
+
+
+def _sinkhorn_c(a, b, c, eps, n_iter, f, g, symmetric, ct=None):
+    """The same iterations as the NumPy loop of sinkhorn(), in plain C over
+    rows (and rows of C^T for the columns), threads over rows."""
+    import ctypes
+
+    lib = _c_sinkhorn_lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    ct = np.ascontiguousarray(c.T) if ct is None else ct
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64).copy()
+    g = np.ascontiguousarray(g, dtype=np.float64).copy()
+    ptr = lambda v: v.ctypes.data_as(dp)  # noqa: E731
+    rc = lib.oracle_sinkhorn(ptr(c), ptr(ct), c.shape[0], c.shape[1], ptr(a), ptr(b), float(eps), int(n_iter),
+                             1 if symmetric else 0, ptr(f), ptr(g))
+    if rc != 0:
+        raise MemoryError("oracle C Sinkhorn: allocation failed")
+    return f, g
+
+
+def sinkhorn(a, b, c, eps, n_iter, f0=None, g0=None, symmetric=True, backend="numpy", ct=None):
     """Algorithm 2 (Sinkhorn) or Algorithm 3 (Sinkhorn-symm), Appendix B.1,
     in the log domain.  Symmetric: both half-steps read iterate n.
-    Alternating: the g update reads the new f."""
+    Alternating: the g update reads the new f.  backend "c" runs the same
+    iterations in the oracle's C loop (sinkhorn.c; ct may pass C^T)."""
     f = np.zeros(len(a)) if f0 is None else np.array(f0, dtype=np.float64)
     g = np.zeros(len(b)) if g0 is None else np.array(g0, dtype=np.float64)
+    if backend == "c":
+        return _sinkhorn_c(a, b, c, eps, n_iter, f, g, symmetric, ct)
+    if backend != "numpy":
+        raise ValueError(f"unknown backend {backend!r}")
     for _ in range(n_iter):
         if symmetric:
             tf = softmin_rows(b, g, c, eps)
@@ -297,7 +348,7 @@ class GWResult:
 
 def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
            f0=None, g0=None, symmetric=True, record=False, inner_tol=None,
-           anneal_final=False, adaptive=False) -> GWResult:
+           anneal_final=False, adaptive=False, backend="numpy") -> GWResult:
     """Algorithm 1 (CNT-GW), Section 5, with a fixed number of outer steps.
 
     Per outer step t: Zbar_j = [Gamma_t Y_j, |Y_j|^2/2]; the squared-norm
@@ -323,7 +374,10 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     is no cap.  The previous plan of step 0 is a x b when gamma0 is None;
     with a given gamma0 the first comparison is after step 1.  Each
     comparison is recorded in GWResult.adaptive_log as (t, e_new, e_old,
-    scale, doubled)."""
+    scale, doubled).
+
+    backend: "numpy", or "c" for the fixed-count Sinkhorn iterations in the
+    oracle's C loop (large problems)."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     X = np.asarray(X, np.float64)
@@ -345,17 +399,19 @@ def cnt_gw(a, b, X, Y, eps_start, eps_end, n_outer, n_inner, gamma0=None,
     for t, eps in enumerate(eps_list):
         zbar = np.concatenate([Y @ gamma.T, 0.5 * np.sum(Y * Y, axis=1, keepdims=True)], axis=1)
         cbar = sqdist(xbar, zbar)
+        cbar_t = np.ascontiguousarray(cbar.T) if backend == "c" else None
         if anneal_final and t == n_outer - 1:
             for it in range(1, n_in + 1):
-                f, g = sinkhorn(a, b, cbar, eps / np.sqrt(it) / 8.0, 1, f, g, symmetric)
+                f, g = sinkhorn(a, b, cbar, eps / np.sqrt(it) / 8.0, 1, f, g, symmetric, backend, cbar_t)
             eps = eps / np.sqrt(max(n_in, 1))
             eps_list[-1] = eps
         elif inner_tol is None:
-            f, g = sinkhorn(a, b, cbar, eps / 8.0, n_in, f, g, symmetric)
+            f, g = sinkhorn(a, b, cbar, eps / 8.0, n_in, f, g, symmetric, backend, cbar_t)
         else:
             f, g = sinkhorn_converged(a, b, cbar, eps / 8.0, f, g, tol=inner_tol)
         epsp = eps / 8.0
         expo = np.exp((f[:, None] + g[None, :] - cbar) / epsp)
+        del cbar_t
         xt = expo.T @ (a[:, None] * X)          # X~_j = sum_i a_i X_i expo_ij
         new_gamma = (b[:, None] * xt).T @ Y
         pi = a[:, None] * b[None, :] * expo
