@@ -185,13 +185,51 @@ int gw_feature_dim(const gw_ctx* ctx, int side, int d);
    initialises Gamma (NULL: Gamma_0 = 0, the product coupling).  Potentials
    start at 0 unless params->use_init_potentials.  Inputs: x (n x dx), a (n),
    y (m x dy), b (m).  Errors: GW_EINVAL for n or m < 1, dims out of range,
-   non-finite inputs, weights <= 0 or |sum - 1| > 1e-5, eps <= 0, counts < 1;
+   non-finite inputs, weights <= 0 or |sum - 1| > 1e-6 (sum taken in FP64),
+   eps <= 0, counts < 1;
    GW_ENUMERIC if the iteration produced non-finite values. */
 gw_status gw_solve(gw_ctx* ctx,
                    const float* x, int64_t n, int dx, const float* a,
                    const float* y, int64_t m, int dy, const float* b,
                    const gw_params* params, const float* gamma0,
                    gw_result* out);
+
+/* ---- Stepwise solve: Algorithm 1 one outer step at a time ----
+   The state of Algorithm 1 between outer steps is (f, g, Gamma_t, t, eps_t)
+   (Algorithm 1; warm starts as in Appendix B.1).  These three calls keep it
+   inside the context, so a caller can run a solve in pieces and synchronise,
+   time or inspect between them:
+     gw_solve_begin   validation and setup exactly as gw_solve (same
+                      inputs, errors and warm start: out->f, out->g are read
+                      when params->use_init_potentials); no outer step yet.
+     gw_solve_advance enqueues up to n_steps further outer steps (prologue,
+                      the step's Sinkhorn iterations, covariance) on the
+                      context's stream and returns without waiting, except
+                      where tol_gamma or adaptive_inner read back one scalar
+                      per step.  *outer_done (host, nullable) receives the
+                      outer steps enqueued so far; once it equals n_outer
+                      (or tol_gamma stopped the loop), further calls do
+                      nothing.  n_steps >= 0.
+     gw_solve_end     the FP64 final check and the outputs of gw_solve
+                      (out->f, out->g, out->gamma and the scalars), then
+                      releases the stepwise solve.  Valid after any number
+                      of outer steps >= 1; the result then describes the
+                      coupling after those steps.
+   begin, advance(k1), advance(k2), ..., end with k1 + k2 + ... = n_outer is
+   the same computation as gw_solve, bit for bit.  One stepwise solve per
+   context: a new gw_solve_begin replaces an unfinished one.  Its device
+   inputs (x, a, y, b, gamma0) must stay valid and unchanged until
+   gw_solve_end.  Other entry points may run on the context in between; the
+   stepwise solve's buffers are its own.  Errors: as gw_solve; GW_ESTATE for
+   advance or end without an active stepwise solve, or end before the first
+   outer step; GW_EINVAL for n_steps < 0. */
+gw_status gw_solve_begin(gw_ctx* ctx,
+                         const float* x, int64_t n, int dx, const float* a,
+                         const float* y, int64_t m, int dy, const float* b,
+                         const gw_params* params, const float* gamma0,
+                         const gw_result* warm);
+gw_status gw_solve_advance(gw_ctx* ctx, int n_steps, int32_t* outer_done);
+gw_status gw_solve_end(gw_ctx* ctx, gw_result* out);
 
 /* Result of gw_sgw. */
 typedef struct {
@@ -380,6 +418,13 @@ typedef struct {
     int64_t launches[GW_PROF_CLASSES];
     double milliseconds[GW_PROF_CLASSES];   /* summed event intervals */
     int64_t entries_per_pass;               /* N * M of the last solve */
+    /* the part of launches / milliseconds from intervals under 20
+       microseconds: at large sizes these are the launches the device-side
+       mode gate turned into no-ops (a stabilised pass in a safe iteration,
+       a retry that was not needed), so (milliseconds - idle) / (launches -
+       idle) is the mean duration of the launches that did the work */
+    int64_t idle_launches[GW_PROF_CLASSES];
+    double idle_milliseconds[GW_PROF_CLASSES];
 } gw_profile;
 
 /* Enable (1) or disable (0) event timing; either call resets the counters.
@@ -412,11 +457,20 @@ typedef struct {
     uint64_t submitted, completed, cancelled, rejected;
     int32_t active, queued;
     double busy_seconds;       /* wall time with at least one active request */
+    uint64_t device_bytes;     /* device memory the server's request slots
+                                  hold now (workspaces and landmark data) */
+    uint64_t peak_device_bytes;/* the largest device_bytes seen */
 } gw_server_stats;
 
 /* Create a server on ctx's device and stream.  max_slots bounds the number
-   of requests resident on the GPU at once; hbm_budget_bytes bounds their
-   total footprint (0 = no bound).  The server runs its own host thread. */
+   of requests resident on the GPU at once.  hbm_budget_bytes (0 = no bound)
+   bounds the device memory of the resident requests: a request is admitted
+   when its planned footprint (every buffer of its solve, its FP64 check and
+   its lifting) fits beside those of the requests already admitted, and a
+   finished request's slot then gives its memory back (without a budget,
+   slots keep their buffers for the next request).  Memory the rocBLAS /
+   rocSOLVER handle of the landmark eigensolve keeps is not counted.  The
+   server runs its own host threads. */
 gw_status gw_server_create(gw_ctx* ctx, int max_slots, size_t hbm_budget_bytes,
                            gw_server** out);
 

@@ -116,6 +116,7 @@ class GwServerStats(ctypes.Structure):
         ("cancelled", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
         ("active", ctypes.c_int32), ("queued", ctypes.c_int32),
         ("busy_seconds", ctypes.c_double),
+        ("device_bytes", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
     ]
 
 
@@ -128,6 +129,8 @@ class GwProfile(ctypes.Structure):
         ("launches", ctypes.c_int64 * GW_PROF_CLASSES),
         ("milliseconds", ctypes.c_double * GW_PROF_CLASSES),
         ("entries_per_pass", ctypes.c_int64),
+        ("idle_launches", ctypes.c_int64 * GW_PROF_CLASSES),
+        ("idle_milliseconds", ctypes.c_double * GW_PROF_CLASSES),
     ]
 
 
@@ -145,6 +148,11 @@ SIGNATURES = {
     "gw_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.POINTER(GwParams), ctypes.c_void_p, ctypes.POINTER(GwResult)]),
+    "gw_solve_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.POINTER(GwParams), ctypes.c_void_p, ctypes.POINTER(GwResult)]),
+    "gw_solve_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+    "gw_solve_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GwResult)]),
     "gw_sgw": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                               ctypes.POINTER(GwParams), ctypes.POINTER(GwSgwResult)]),

@@ -92,7 +92,8 @@ class Context:
     def profile(self) -> dict:
         pr = L.GwProfile()
         self._check(self.lib.gw_get_profile(self.h, ctypes.byref(pr)))
-        out = {name: {"launches": int(pr.launches[k]), "ms": float(pr.milliseconds[k])}
+        out = {name: {"launches": int(pr.launches[k]), "ms": float(pr.milliseconds[k]),
+                      "idle_launches": int(pr.idle_launches[k]), "idle_ms": float(pr.idle_milliseconds[k])}
                for k, name in enumerate(L.PROF_NAMES)}
         out["entries_per_pass"] = int(pr.entries_per_pass)
         return out
@@ -145,6 +146,49 @@ class Context:
         r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
         self._check(self.lib.gw_solve(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
                                       ctypes.byref(prm), _ptr(g0t), ctypes.byref(r)))
+        return _result_dict(r, f, g, gamma)
+
+    def solve_begin(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
+                    precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, tol_gamma=0.0,
+                    anneal_final=False, adaptive_inner=False):
+        """Set up a stepwise solve (gw_solve_begin): same arguments as
+        solve().  The inputs are held until solve_end()."""
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        g0t = None if gamma0 is None else _dev_f32(gamma0, "gamma0")
+        warm = L.GwResult()
+        f0t = g0t_ = None
+        if f0 is not None and g0 is not None:
+            f0t, g0t_ = _dev_f32(f0, "f0"), _dev_f32(g0, "g0")
+            warm.f, warm.g = f0t.data_ptr(), g0t_.data_ptr()
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode,
+                          f0t is not None, tol_gamma, anneal_final, adaptive_inner)
+        self._stepped = (x, a, y, b, g0t)  # kept alive for the library
+        self._check(self.lib.gw_solve_begin(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
+                                            ctypes.byref(prm), _ptr(g0t), ctypes.byref(warm)))
+
+    def solve_advance(self, n_steps: int = 1) -> int:
+        """Enqueue up to n_steps outer steps of the stepwise solve
+        (gw_solve_advance); returns the outer steps enqueued so far."""
+        done = ctypes.c_int32()
+        self._check(self.lib.gw_solve_advance(self.h, int(n_steps), ctypes.byref(done)))
+        return int(done.value)
+
+    def solve_end(self) -> dict:
+        """Final check and outputs of the stepwise solve (gw_solve_end)."""
+        x, _, y, _, _ = self._stepped
+        n, m = x.shape[0], y.shape[0]
+        D, E = self.feature_dim(0, x.shape[1]), self.feature_dim(1, y.shape[1])
+        f = torch.empty(n, dtype=torch.float32, device=x.device)
+        g = torch.empty(m, dtype=torch.float32, device=x.device)
+        gamma = torch.empty((D, E), dtype=torch.float32, device=x.device)
+        r = L.GwResult()
+        r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
+        try:
+            self._check(self.lib.gw_solve_end(self.h, ctypes.byref(r)))
+        finally:
+            self._stepped = None
         return _result_dict(r, f, g, gamma)
 
     def sgw(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,

@@ -142,6 +142,54 @@ gw_status gw_solve(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* 
     return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, nullptr, nullptr, nullptr, nullptr, false);
 }
 
+gw_status gw_solve_begin(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
+                         int dy, const float* b, const gw_params* params, const float* gamma0, const gw_result* warm) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    ctx->c.stepped.reset();
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = gwr::validate_inputs(ctx->c, x, n, dx, a, y, m, dy, b, params, "p.");
+    if (!st.good()) return ret(ctx, st);
+    if (params->use_init_potentials && (!warm || !warm->f || !warm->g))
+        return ret(ctx, gwr::fail(GW_EINVAL, "warm start needs warm->f and warm->g"));
+    std::unique_ptr<gwr::Solve> solve(new (std::nothrow) gwr::Solve(ctx->c, "p."));
+    if (!solve) return ret(ctx, gwr::fail(GW_ENOMEM, "stepwise solve"));
+    const float* f0 = params->use_init_potentials ? warm->f : nullptr;
+    const float* g0 = params->use_init_potentials ? warm->g : nullptr;
+    st = solve->setup(x, n, dx, a, y, m, dy, b, *params, gamma0, f0, g0, ctx->c.side[0].kind, ctx->c.side[1].kind,
+                      ctx->c.stream);
+    if (!st.good()) return ret(ctx, st);
+    ctx->c.stepped = std::move(solve);
+    return ret(ctx, Status::ok());
+}
+
+gw_status gw_solve_advance(gw_ctx* ctx, int n_steps, int32_t* outer_done) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (n_steps < 0) return ret(ctx, gwr::fail(GW_EINVAL, "n_steps must be >= 0"));
+    gwr::Solve* solve = ctx->c.stepped.get();
+    if (!solve) return ret(ctx, gwr::fail(GW_ESTATE, "no stepwise solve: call gw_solve_begin first"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st;
+    for (int k = 0; k < n_steps && !solve->done() && st.good(); ++k) st = solve->outer_step();
+    if (outer_done) *outer_done = solve->outer_done();
+    if (!st.good()) ctx->c.stepped.reset();
+    return ret(ctx, st);
+}
+
+gw_status gw_solve_end(gw_ctx* ctx, gw_result* out) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (!out) return ret(ctx, gwr::fail(GW_EINVAL, "result is NULL"));
+    gwr::Solve* solve = ctx->c.stepped.get();
+    if (!solve) return ret(ctx, gwr::fail(GW_ESTATE, "no stepwise solve: call gw_solve_begin first"));
+    if (solve->outer_done() < 1) return ret(ctx, gwr::fail(GW_ESTATE, "no outer step has run yet"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = solve->finish(out);
+    ctx->c.stepped.reset();
+    return ret(ctx, st);
+}
+
 gw_status gw_loss_and_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
                            int dy, const float* b, const gw_params* params, const float* gamma0, gw_result* out,
                            float* grad_x, float* grad_a, float* grad_y, float* grad_b) {
@@ -313,6 +361,8 @@ gw_status gw_get_profile(gw_ctx* ctx, gw_profile* out) {
     for (int k = 0; k < GW_PROF_CLASSES; ++k) {
         out->launches[k] = ctx->c.prof.launches[k];
         out->milliseconds[k] = ctx->c.prof.ms[k];
+        out->idle_launches[k] = ctx->c.prof.idle_launches[k];
+        out->idle_milliseconds[k] = ctx->c.prof.idle_ms[k];
     }
     out->entries_per_pass = ctx->c.prof.entries;
     return ret(ctx, Status::ok());

@@ -96,6 +96,7 @@ void* Ctx::host_stage(size_t bytes, Status* st) {
 }
 
 Ctx::~Ctx() {
+    stepped.reset();
     if (stage_) (void)hipHostFree(stage_);
 }
 
@@ -131,6 +132,10 @@ Status Profiler::collect(hipStream_t s) {
         if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
             ms[p.cls] += t;
             launches[p.cls] += 1;
+            if (t < IDLE_MS) {
+                idle_ms[p.cls] += t;
+                idle_launches[p.cls] += 1;
+            }
         }
         pool_.push_back(p.a);
         pool_.push_back(p.b);
@@ -148,6 +153,8 @@ void Profiler::reset() {
     for (int k = 0; k < GW_PROF_CLASSES; ++k) {
         launches[k] = 0;
         ms[k] = 0.0;
+        idle_launches[k] = 0;
+        idle_ms[k] = 0.0;
     }
 }
 
@@ -207,7 +214,8 @@ static Status device_check(Ctx& c, const float* x, int64_t nx, const float* w, i
     if (hf & 2) return fail(GW_EINVAL, std::string("weights of ") + what + " must be > 0");
     double s = 0.0;
     for (double v : hp) s += v;
-    if (std::fabs(s - 1.0) > 1e-5) return fail(GW_EINVAL, std::string("weights of ") + what + " must sum to 1");
+    if (std::fabs(s - 1.0) > 1e-6)
+        return fail(GW_EINVAL, std::string("weights of ") + what + " must sum to 1 within 1e-6");
     *wsum = s;
     return Status::ok();
 }
@@ -450,6 +458,10 @@ Status Solve::buffers(bool dry) {
     momy_ = getd("momy", 2 + E_ * E_ + E_);
     mompart_ = getd("mompart", std::max(gwk::moments_part_doubles(n_, D_), gwk::moments_part_doubles(m_, E_)));
     chk_ = geo_.path == 0 ? getd("chk", gwk::check64_part_doubles(n_, m_)) : nullptr;
+    // per-row and per-column FP64 sums of the final check
+    r64_ = getd("r64", n_);
+    kl64_ = getd("kl64", n_);
+    c64_ = getd("c64", m_);
     return st;
 }
 
@@ -721,12 +733,9 @@ Status Solve::finish_enqueue(gw_result* out) {
 // FP64 check of the current coupling (f_t, g_t, Gamma_{t-1}): row sums, KL
 // and column sums, reduced into scal_[4] (Err) and scal_[5] (KL).
 Status Solve::enqueue_check() {
-    Status st;
-    auto& ws = c_.ws;
-    double* r64 = ws.get_t<double>(tag_ + "r64", n_, &st);
-    double* kl64 = ws.get_t<double>(tag_ + "kl64", n_, &st);
-    double* c64 = ws.get_t<double>(tag_ + "c64", m_, &st);
-    if (!st.good()) return st;
+    double* r64 = r64_;
+    double* kl64 = kl64_;
+    double* c64 = c64_;
     c_.prof.begin(GW_PROF_CHECK, st_);
     if (geo_.path == 1) {
         const float kap = (float)kappa_;

@@ -102,6 +102,10 @@ class Profiler {
     ~Profiler();
     int64_t launches[GW_PROF_CLASSES] = {};
     double ms[GW_PROF_CLASSES] = {};
+    // intervals under IDLE_MS (mode-gated launches at large sizes)
+    static constexpr float IDLE_MS = 0.02f;
+    int64_t idle_launches[GW_PROF_CLASSES] = {};
+    double idle_ms[GW_PROF_CLASSES] = {};
     int64_t entries = 0;
 
    private:
@@ -115,6 +119,8 @@ class Profiler {
     Pair cur_{};
 };
 
+class Solve;
+
 struct Ctx {
     Profiler prof;
     int device = 0;
@@ -124,6 +130,9 @@ struct Ctx {
     SideCfg side[2];
     void* rocblas = nullptr;  // rocblas_handle, created on first eigensolve
     std::mutex mu;
+    // The solve of the stepwise entry points (gw_solve_begin / advance /
+    // end), kept between calls; its buffers carry their own name prefix.
+    std::unique_ptr<Solve> stepped;
     // Pinned host staging for result readback, grown on demand; bytes = 0
     // returns the current buffer.
     void* host_stage(size_t bytes, Status* st);
@@ -142,7 +151,7 @@ Status lift_side(Ctx& c, int side, const float* x, int64_t n, int d, const float
                  const std::string& tag);
 
 // Device check of nx values of x (finite) and nw weights (finite, > 0,
-// summing to 1 within 1e-5); waits for the result.
+// summing to 1 within 1e-6, FP64 sum); waits for the result.
 Status check_points(Ctx& c, const float* x, int64_t nx, const float* w, int64_t nw, const std::string& tag,
                     const char* what);
 
@@ -259,6 +268,7 @@ class Solve {
     int* ctl_ = nullptr;
     double *momx_ = nullptr, *momy_ = nullptr, *mompart_ = nullptr;
     double* chk_ = nullptr;  // FP64 check partials (MFMA path)
+    double *r64_ = nullptr, *kl64_ = nullptr, *c64_ = nullptr;  // FP64 check sums
     int cov_tw_ = 0;
     // adaptive Sinkhorn counts (Algorithm 6)
     int n_inner_cur_ = 0, doublings_ = 0;

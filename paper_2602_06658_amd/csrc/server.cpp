@@ -21,11 +21,13 @@
 // Requests are admitted while a slot is free and their planned device
 // footprint fits the HBM budget.  Request contexts (workspace, pinned
 // staging, event) are pooled and reused, so the rounds never wait for a
-// device free.
+// device free; with a budget, a returned slot frees its workspace so that
+// idle slots hold no memory the budget does not see.
 //
 // Each request runs the same kernels as gw_solve with the same per-problem
 // arguments, so its result does not depend on what else is in the batch.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -64,7 +66,7 @@ struct Request {
     double latency = 0.0;
     gw_result res{};
     size_t footprint = 0;
-    bool cancel = false;
+    std::atomic<bool> cancel{false};
     // GPU-side state, owned by one thread at a time (setup, then rounds)
     Slot* slot = nullptr;
     std::unique_ptr<gwr::Solve> solve;
@@ -92,7 +94,7 @@ struct gw_server {
     int in_flight = 0;                    // admitted and not yet completed
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     gw_server_stats stats{};
-    size_t resident = 0;
+    size_t resident = 0;                  // planned footprints of admitted requests
     void* rocblas = nullptr;              // used by the setup thread only
     // round thread only
     std::vector<Request*> active, finishing;
@@ -111,6 +113,47 @@ void configure_sides(gwr::Ctx& c, const gw_request& r) {
         sc.explicit_idx.clear();
         sc.lm.fitted = false;
     }
+}
+
+// Device bytes a slot holds: its workspace and landmark data.
+size_t slot_bytes(const Slot& sl) {
+    size_t b = sl.ctx->ws.total();
+    for (int k = 0; k < 2; ++k) {
+        const gwr::Landmarks& lm = sl.ctx->side[k].lm;
+        if (lm.fitted) b += 4 * ((size_t)lm.n_l * (lm.d_in + lm.dim + 1) + lm.dim);
+    }
+    return b;
+}
+
+// Update the held-memory statistics by delta (under s->mu).
+void account(gw_server* s, int64_t delta) {
+    s->stats.device_bytes = (uint64_t)((int64_t)s->stats.device_bytes + delta);
+    s->stats.peak_device_bytes = std::max(s->stats.peak_device_bytes, s->stats.device_bytes);
+}
+
+// Planned device footprint of a request: every buffer of its solve
+// (including the FP64 check's sums) and, for the |x - x'|^p penalty, the
+// lifting's buffers: the landmark kernel (n_l^2 doubles), eigen-workspace
+// (3 n_l doubles), the Nystrom features before centring (n_pad x D floats),
+// the centring partials and the landmark data, per side.
+size_t request_footprint(const gw_request& r) {
+    gwr::Ctx probe;
+    configure_sides(probe, r);
+    size_t b = gwr::Solve::plan_bytes(probe, r.n, r.dx, r.m, r.dy, r.params);
+    if (b == 0) return 0;
+    const int64_t np[2] = {(r.n + 31) / 32 * 32, (r.m + 31) / 32 * 32};
+    const int64_t nn[2] = {r.n, r.m};
+    const int din[2] = {r.dx, r.dy};
+    for (int k = 0; k < 2; ++k) {
+        const int D = r.penalty == GW_PEN_POWER ? r.lifted_dim : din[k];
+        b += 8 * (gwk::centre_part_doubles(nn[k], D) + D) + 2 * (16 + 64 * 8);
+        if (r.penalty == GW_PEN_POWER) {
+            const size_t nl = (size_t)std::max(0, r.n_landmarks);
+            b += 8 * (nl * nl + 3 * nl + 1) + 8 * nl + 4 * (size_t)np[k] * D;
+            b += 4 * (nl * (din[k] + D + 1) + D);
+        }
+    }
+    return b + 64 * 256;  // alignment slack
 }
 
 Slot* acquire_slot(gw_server* s) {
@@ -132,15 +175,20 @@ Slot* acquire_slot(gw_server* s) {
 }
 
 // Return a slot whose GPU work has completed.  Its landmark data is freed
-// (only read while lifting); the workspace stays for the next request.
+// (only read while lifting); the workspace stays for the next request unless
+// the server has a budget, which idle memory would escape.
 void release_slot(gw_server* s, Request* q) {
     q->solve.reset();
     Slot* sl = q->slot;
     q->slot = nullptr;
     if (!sl) return;
     if (sl->ctx->rocblas == s->rocblas) sl->ctx->rocblas = nullptr;  // shared handle stays
+    const size_t before = slot_bytes(*sl);
     gwr::release_landmarks(*sl->ctx);
+    if (s->budget) sl->ctx->ws.release_all();
+    const size_t after = slot_bytes(*sl);
     std::lock_guard<std::mutex> lk(s->mu);
+    account(s, (int64_t)after - (int64_t)before);
     for (auto it = s->used_slots.begin(); it != s->used_slots.end(); ++it)
         if (it->get() == sl) {
             s->free_slots.push_back(std::move(*it));
@@ -168,6 +216,17 @@ void complete(gw_server* s, Request* q, ReqState st, gw_status code, const std::
 gwr::Status start(gw_server* s, Request* q) {
     q->slot = acquire_slot(s);
     gwr::Ctx& c = *q->slot->ctx;
+    const size_t before = slot_bytes(*q->slot);
+    struct Account {  // record the slot's growth on every exit path
+        gw_server* s;
+        Slot* sl;
+        size_t before;
+        ~Account() {
+            const size_t after = slot_bytes(*sl);
+            std::lock_guard<std::mutex> lk(s->mu);
+            account(s, (int64_t)after - (int64_t)before);
+        }
+    } acct{s, q->slot, before};
     c.stream = s->setup_stream;
     configure_sides(c, q->r);
     if (q->r.penalty == GW_PEN_POWER) {
@@ -436,14 +495,7 @@ gw_status gw_server_submit(gw_server* s, const gw_request* req, uint64_t* ticket
     auto q = std::make_unique<Request>();
     q->r = *req;
     q->t_submit = Clock::now();
-    {
-        // footprint of the solve's buffers for admission (landmark data of
-        // the |x - x'|^p penalty comes on top: n_l^2 doubles per side)
-        gwr::Ctx probe;
-        configure_sides(probe, *req);
-        q->footprint = gwr::Solve::plan_bytes(probe, req->n, req->dx, req->m, req->dy, req->params);
-        if (req->penalty == GW_PEN_POWER) q->footprint += 2 * (size_t)req->n_landmarks * req->n_landmarks * 8;
-    }
+    q->footprint = request_footprint(*req);
     std::lock_guard<std::mutex> lk(s->mu);
     s->stats.submitted++;
     if (q->footprint == 0 || (s->budget && q->footprint > s->budget)) {

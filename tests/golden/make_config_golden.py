@@ -3,6 +3,7 @@ schedules (inputs from tests/config_cases.py).  Calls only oracle/ and
 workloads/ (through config_cases).
 
     python tests/golden/make_config_golden.py c3sub   # c3sub5000_oracle.json (~10 min)
+    python tests/golden/make_config_golden.py c3sub_inputs   # c3sub5000_inputs.npz
     python tests/golden/make_config_golden.py c4      # c4_samples_oracle.json
     python tests/golden/make_config_golden.py c2      # c2_oracle.json + .npz (~1.5 h)
 
@@ -94,6 +95,17 @@ def c3sub():
           f"({out['oracle_seconds']:.0f} s)", flush=True)
 
 
+def c3sub_inputs():
+    """The 5,000-point case's single-precision features and weights (what
+    the GPU receives), for the bench's parity leg and its CPU baseline,
+    which do not rebuild them with the oracle's kernel PCA."""
+    case = CC.c3_subsample()
+    np.savez_compressed(os.path.join(HERE, f"{case['name']}_inputs.npz"), X=case["X"].astype(np.float32),
+                        a=case["a"].astype(np.float32), Y=case["Y"].astype(np.float32),
+                        b=case["b"].astype(np.float32))
+    print(f"{case['name']} inputs written", flush=True)
+
+
 def c2():
     t0 = time.time()
     case = CC.c2_full()
@@ -127,4 +139,4 @@ def c4():
 
 if __name__ == "__main__":
     for what in sys.argv[1:] or ["c3sub", "c4"]:
-        {"c3sub": c3sub, "c2": c2, "c4": c4}[what]()
+        {"c3sub": c3sub, "c3sub_inputs": c3sub_inputs, "c2": c2, "c4": c4}[what]()

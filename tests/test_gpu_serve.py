@@ -90,6 +90,31 @@ def test_budget_admission_and_rejection(gw):
     assert all(np.isfinite(o["loss_lift"]) for o in outs)
 
 
+def test_budget_bounds_device_memory_with_mixed_sizes(gw):
+    # uneven requests through a budget of about two of the largest: the
+    # memory the slots hold (workspaces and landmark data, reported by the
+    # server) never exceeds it, because admission counts every buffer a
+    # request allocates and finished slots give their memory back
+    reqs = _requests(10, lo=600, hi=6000, seed=4250)
+    ctx = gw.Context()
+    probe = gw.Server(ctx, max_slots=1)
+    big = max(range(len(reqs)), key=lambda i: reqs[i][0].shape[0] * reqs[i][2].shape[0])
+    probe.wait(_submit(probe, *reqs[big], seed=60))
+    one = probe.stats()["peak_device_bytes"]
+    probe.close()
+    budget = int(2.2 * one)
+    srv = gw.Server(ctx, max_slots=6, hbm_budget_bytes=budget)
+    tickets = [_submit(srv, *r, seed=60 + i) for i, r in enumerate(reqs)]
+    outs = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    print("largest request holds", one, "budget", budget, "peak", st["peak_device_bytes"], "now", st["device_bytes"])
+    assert all(np.isfinite(o["loss_lift"]) for o in outs)
+    assert st["completed"] == len(reqs)
+    assert 0 < st["peak_device_bytes"] <= budget
+    assert st["device_bytes"] == 0
+
+
 def test_cancel_queued(gw):
     reqs = _requests(3, lo=2000, hi=2500, seed=4300)
     ctx = gw.Context()
