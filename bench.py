@@ -1,16 +1,27 @@
 """Throughput of the CNT-GW hot path on one MI355X.
 
-One step = one complete Algorithm 1 solve of the 200k x 200k workload
-(3-D 8-component Gaussian mixtures, |x - x'| penalty lifted to D = E = 64
-features by landmark kernel PCA, eps annealed 0.1 -> 0.005 over 30 outer
-steps of 100 symmetric Sinkhorn iterations, BF16 feature products on MFMA
-with FP32 log-sum-exp and potentials, FP64 final marginal check).  The
-lifted features are resident in HBM before the timed region; lifting is
-timed separately.
+Workload: N = M = 200,000 points of a 3-D 8-component Gaussian mixture, the
+target a noisy rigid motion of the source, |x - x'| penalty lifted to
+D = E = 64 features by landmark kernel PCA (2048 landmarks), eps annealed
+0.1 -> 0.005 over 30 outer steps of 100 symmetric Sinkhorn iterations
+(Algorithm 1 with Algorithm 3).  The lifted features are resident in HBM
+before the timed region; lifting is timed apart.
 
-metric: GW cost entries / s = N * M * n_outer * n_inner / solve time.
+One step = one outer step of Algorithm 1 (prologue, 100 Sinkhorn
+iterations, covariance) in the plain FP32 form, run through the stepwise
+solve (gw_solve_begin / gw_solve_advance / gw_solve_end), so that steps
+0..warmup-1 are the untimed warm-up and the next `steps` outer steps are
+timed; a whole solve is 30 steps plus the FP64 final check.
 
-Prints one JSON line.
+metric: GW cost entries / s = N * M * n_inner * steps / timed seconds.
+
+Beside the headline the line reports: the whole-solve figures of the FP32
+form, the BF16 and split-BF16 forms, the relative error against the FP64
+oracle of every form on the seeded 5,000 + 5,000 subsample at the same
+schedule (stored oracle results), the serving workload (solves/s, p50/p99
+latency, error of sampled requests against stored oracle results), the
+roofline of the dominant kernel, and the oracle timed on the host's cores.
+Progress goes to stderr; one JSON line to stdout.
 """
 from __future__ import annotations
 
@@ -24,19 +35,27 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-# MI355X published peaks and unit counts
+# MI355X published dense peaks (TFLOP/s) and unit counts
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 PEAK_HBM_GBS = 8000.0
 CUS, SIMDS_PER_CU, LANES_PER_CLK, CLOCK_HZ = 256, 4, 16, 2.4e9
-PEAK_BF16_TFLOPS = 2500.0
-# VALU issue slots per entry of the stabilised pass: one 2^x on the
-# transcendental unit and two FP32 adds (row and column accumulation).
-EXP_SLOTS = 2.0      # v_exp_f32 issues at half the FP32 rate on gfx950 (measured)
-ADD_SLOTS = 2.0
-
+# algorithmic feature flops per entry (the D-dot of X_i . Z_j at D = 64)
+# and what each form's MFMA tile executes (bias slots and BF16 splits
+# included; see the operand layouts)
+ALGO_FLOPS_PER_ENTRY = 2 * 64
+MFMA_FLOPS_PER_ENTRY = {"fp32": 2 * (64 + 8), "bf16": 2 * (64 + 16), "bf16x3": 2 * (3 * 64 + 16)}
 
 PASS_SOURCES = ["k_sinkhorn.hip", "gw_cores.h", "gw_device.h", "gw_layout.h", "gw_kernels.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_stab_gmm200k_bf16_hbm_traffic.txt")
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_file(prec: str) -> str:
+    return os.path.join(ROOT, "profiles", f"k_pass_stab_gmm200k_{prec}_hbm_traffic.txt")
 
 
 def pass_source_hash() -> str:
@@ -54,14 +73,15 @@ def pass_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
+def recorded_traffic(prec: str):
     """HBM bytes per launch of the stabilised pass from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
     or None if the summary is missing or was taken on other sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(prec)
+    if not os.path.exists(path):
         return None
     fields = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for ln in fh:
             if ":" in ln:
                 k, v = ln.split(":", 1)
@@ -74,26 +94,58 @@ def recorded_traffic():
         return None
 
 
-def alu_peak_entries_per_s() -> float:
-    lane_ops = CUS * SIMDS_PER_CU * LANES_PER_CLK * CLOCK_HZ
-    return lane_ops / (EXP_SLOTS + ADD_SLOTS)
+def measure_peaks() -> dict | None:
+    """Instruction rates from the committed microbenchmark
+    (paper_2602_06658_amd/peaks/peaks.hip, built as libgwpeaks.so) and the
+    ALU roofline of the single-exponential pass derived from them."""
+    import ctypes
+
+    path = os.path.join(ROOT, "paper_2602_06658_amd", "libgwpeaks.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    out = (ctypes.c_double * 6)()
+    if lib.gwp_measure(out) != 0:
+        return None
+    fma, exp_sub, entry, bf16, f32, clk = (float(v) for v in out)
+    simds = CUS * SIMDS_PER_CU
+    # FP32 lanes a SIMD retires per clock on v_fma_f32 (32 on gfx950: a
+    # wave64 FMA issues in two cycles), and the issue cost of one v_exp_f32
+    # in FMA slots, from (exp + sub) against plain FMA
+    lanes = fma / (simds * clk) if clk > 0 else float("nan")
+    exp_slots = fma / exp_sub - 1.0
+    lanes_r = 32.0 if abs(lanes - 32.0) < 4.0 else lanes
+    return {"source": "paper_2602_06658_amd/peaks/peaks.hip", "fma_per_s": fma, "exp_sub_per_s": exp_sub,
+            "pass_valu_entries_per_s": entry, "mfma_bf16_tflops": bf16 / 1e12, "mfma_f32_tflops": f32 / 1e12,
+            "shader_clock_ghz": clk / 1e9, "fma_lanes_per_clock_per_simd": lanes, "exp_issue_slots": exp_slots,
+            # the ALU model of the stabilised pass: one exp and two adds per
+            # entry, on 1024 SIMDs at the published 2.4 GHz
+            "alu_model_entries_per_s": simds * lanes_r * CLOCK_HZ / (exp_slots + 2.0),
+            "alu_model": "1024 SIMDs x 32 FP32 lanes per clock x 2.4 GHz / (exp issue slots + 2 adds) per entry"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--dim", type=int, default=64)
     ap.add_argument("--landmarks", type=int, default=2048)
     ap.add_argument("--n-outer", type=int, default=30)
     ap.add_argument("--n-inner", type=int, default=100)
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
-    ap.add_argument("--compare", action="store_true", help="also time FP32 and split-BF16 on one outer step")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x3"],
+                    help="form of the headline (timed) steps")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="optional legs are skipped when they would end after this many seconds of the run")
+    ap.add_argument("--no-finish", action="store_true",
+                    help="do not run the headline solve's remaining outer steps and final check (profiling runs)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / split-BF16 forms")
+    ap.add_argument("--no-whole-bf16", action="store_true", help="skip the whole BF16 solve")
+    ap.add_argument("--no-parity", action="store_true", help="skip the 5k subsample parity leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=3000)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="bound on the single-thread CPU baseline run (seconds)")
     ap.add_argument("--save-features", default=None,
                     help="write the lifted features and weights to this .npz after lifting")
     ap.add_argument("--features", default=None,
@@ -180,26 +232,57 @@ def serve_bench(args, gwm, torch, dev) -> dict:
         res = {"solves_per_s": len(reqs) / wall, "wall_s": wall, "entries_per_s": work / wall,
                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                "max_marginal_err": float(max(o["marginal_err"] for o in outs))}
-        print(f"serving: {slots} slot(s), {'open loop' if gaps is not None else 'all at once'}: "
-              f"{res['solves_per_s']:.2f} solves/s, p50 {res['p50_latency_s']:.3f} s, "
-              f"p99 {res['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
+        log(f"serving: {slots} slot(s), {'open loop' if gaps is not None else 'all at once'}: "
+            f"{res['solves_per_s']:.2f} solves/s, p50 {res['p50_latency_s']:.3f} s, "
+            f"p99 {res['p99_latency_s']:.3f} s")
+        run.outs = outs
         return res
 
     cap = run(args.serve_slots, None)
     rate = args.serve_load * cap["solves_per_s"]
     gaps = arrivals / rate  # the trace is a unit-rate Poisson process
     batched = run(args.serve_slots, gaps)
+    oracle_err = served_oracle_error(run.outs, args)
     single = run(1, gaps)
     out = {"workload": f"{len(reqs)} requests, N, M log-uniform in [1e3, 5e4], d in {{2, 3}}, |x-x'| lifted to "
                        f"D=32 ({args.serve_landmarks} landmarks), eps 0.01, 20x50, {args.serve_precision}",
            "capacity_solves_per_s": cap["solves_per_s"], "capacity_entries_per_s": cap["entries_per_s"],
            "arrival_rate_per_s": rate, "batched": batched, "one_at_a_time": single,
-           "slots": args.serve_slots}
+           "slots": args.serve_slots, "oracle_error": oracle_err}
     loads = [float(v) for v in args.serve_sweep.split(",") if v.strip()]
     if loads:
         out["sweep"] = {f"{ld:g}": dict(run(args.serve_slots, arrivals / (ld * cap["solves_per_s"])),
                                         arrival_rate_per_s=ld * cap["solves_per_s"]) for ld in loads}
     return out
+
+
+def served_oracle_error(outs, args) -> dict | None:
+    """Relative loss error of the sampled served requests against the FP64
+    oracle's stored results (tests/golden/c4_samples_oracle.json: Algorithm 1
+    on the oracle's landmark kernel PCA of the same requests, with the
+    library's seeded landmark choice).  The served requests lift their own
+    features on the GPU, so the figure includes the eigensolver difference."""
+    path = os.path.join(GOLDEN, "c4_samples_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        gold = json.load(fh)
+    if gold.get("landmarks") != args.serve_landmarks:
+        return None
+    rows = []
+    for r in gold["requests"]:
+        k = r["request"]
+        if k >= len(outs):
+            continue
+        o = outs[k]
+        rows.append({"request": k, "n": r["n"], "m": r["m"],
+                     "rel_loss_err": abs(o["loss_lift"] - r["loss_lift"]) / abs(r["loss_lift"]),
+                     "marginal_err": o["marginal_err"], "oracle_marginal_err": r["marginal_error"]})
+    if not rows:
+        return None
+    return {"precision": args.serve_precision, "requests": rows,
+            "max_rel_loss_err": max(r["rel_loss_err"] for r in rows),
+            "reference": "FP64 oracle, tests/golden/c4_samples_oracle.json"}
 
 
 def sgw_bench(args, gwm, torch, dev) -> dict:
@@ -366,30 +449,6 @@ def multiseed_bench(args, gwm, torch, dev) -> dict:
     return out
 
 
-def cpu_baseline(prob, n_sample: int, iters: int) -> dict:
-    """The FP64 oracle (as it stands) on a seeded subsample of the same
-    workload: one outer step of `iters` symmetric Sinkhorn iterations plus the
-    covariance, single-threaded BLAS."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import gw_oracle as O
-    from workloads import landmark_indices, subsample
-
-    sub = subsample(prob, n_sample, n_sample, seed=3999)
-    lmx = O.fit_landmarks(sub.x[landmark_indices(sub.n, 512, 11)], 1.0, prob.lifted_dim)
-    lmy = O.fit_landmarks(sub.y[landmark_indices(sub.m, 512, 12)], 1.0, prob.lifted_dim)
-    X = O.landmark_features(sub.x, sub.a, lmx)
-    Y = O.landmark_features(sub.y, sub.b, lmy)
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        O.cnt_gw(sub.a, sub.b, X, Y, prob.eps_start, prob.eps_start, 1, iters)
-        dt = time.perf_counter() - t0
-    return {"value": sub.n * sub.m * iters / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sub.n}x{sub.m} subsample of the 200k workload, landmark kPCA D={prob.lifted_dim} "
-                      f"(512 landmarks), 1 outer step x {iters} symmetric Sinkhorn iterations at eps="
-                      f"{prob.eps_start}, FP64 NumPy, {dt:.1f} s"}
-
-
 def msgw_bench(args, gwm, torch, X, a, Y, b, prob) -> dict:
     """Multiscale-GW (Algorithm 7) on the lifted 200,000-point features
     against the plain solve with the same schedule: coarsening ratio
@@ -459,12 +518,208 @@ def kpca_bench(args, gwm, torch, prob, x, a, X_landmark) -> dict:
             "landmarks": args.landmarks}
 
 
+def stepwise_solve(ctx, torch, X, a, Y, b, prob, args, prec, warmup, steps, finish=True):
+    """Algorithm 1 on the lifted features, one outer step per call of
+    gw_solve_advance.  The first `warmup` outer steps are untimed; the next
+    `steps` are timed between two device synchronisations, with profiling
+    on; every step is synchronised so its duration is known.  A schedule
+    that runs out inside the timed steps starts a new solve (inside the
+    timed region).  With finish, the remaining outer steps run untimed and
+    the solve ends with the FP64 check."""
+    sched = dict(eps_start=prob.eps_start, eps_end=prob.eps_end, n_outer=args.n_outer, n_inner=args.n_inner,
+                 precision=prec)
+    step_s = []
+
+    def one():
+        t0 = time.perf_counter()
+        done = ctx.solve_advance(1)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t0)
+        return done
+
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    ctx.solve_begin(X, a, Y, b, **sched)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_begin
+    done = 0
+    for _ in range(warmup):
+        if done >= args.n_outer:
+            ctx.solve_end()
+            ctx.solve_begin(X, a, Y, b, **sched)
+            step_s.clear()
+        done = one()
+    ctx.set_profiling(True)
+    restarts = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if done >= args.n_outer:
+            ctx.solve_end()
+            ctx.solve_begin(X, a, Y, b, **sched)
+            restarts += 1
+        done = one()
+        if k % 5 == 4 or k == steps - 1:
+            log(f"{prec}: timed step {k + 1}/{steps} (outer step {done} of {args.n_outer}), "
+                f"{step_s[-1]:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    out = {"elapsed_s": elapsed, "profile": prof, "restarts": restarts, "setup_s": setup_s}
+    if finish:
+        while done < args.n_outer:
+            done = one()
+        t1 = time.perf_counter()
+        res = ctx.solve_end()
+        torch.cuda.synchronize()
+        end_s = time.perf_counter() - t1
+        out["result"] = res
+        if restarts == 0 and len(step_s) == args.n_outer:
+            out["whole_solve_s"] = setup_s + sum(step_s) + end_s
+        out["end_s"] = end_s
+    return out
+
+
+def pass_figures(prof, cls="pass_stab"):
+    """Launches that did the work and their mean duration (mode-gated
+    launches excluded)."""
+    st = prof[cls]
+    n = st["launches"] - st["idle_launches"]
+    ms = st["ms"] - st["idle_ms"]
+    return n, (ms / n if n > 0 else None)
+
+
+def form_step(ctx, torch, X, a, Y, b, prob, args, prec, warm) -> dict:
+    """One outer step of 100 iterations at the last temperature, warm
+    started from the headline solve's final potentials and map (the regime
+    of the late, stabilised steps), in form `prec`: entries/s and the
+    stabilised pass's mean launch time."""
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.solve(X, a, Y, b, prob.eps_end, prob.eps_end, 1, args.n_inner, precision=prec,
+                  gamma0=warm["gamma"], f0=warm["f"], g0=warm["g"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    n_l, avg_ms = pass_figures(prof)
+    entries = float(X.shape[0]) * Y.shape[0]
+    out = {"entries_per_s_one_outer_step": entries * args.n_inner / dt, "seconds": dt,
+           "pass_launches": n_l, "pass_avg_ms": avg_ms, "safe_iters": r["safe_iters"],
+           "marginal_err": r["marginal_err"]}
+    if avg_ms:
+        out["pass_entries_per_s"] = entries / (avg_ms * 1e-3)
+        out["pass_mfma_tflops"] = MFMA_FLOPS_PER_ENTRY[prec] * entries / (avg_ms * 1e-3) / 1e12
+    return out
+
+
+def subsample_parity(gwm, torch, dev, args) -> dict | None:
+    """Every form on the seeded 5,000 + 5,000 subsample of the workload at
+    the full schedule (eps 0.1 -> 0.005, 30 x 100) against the FP64 oracle's
+    stored result for the same features (tests/golden/c3sub5000_*): relative
+    loss error, marginal errors, and the singular values of the final map
+    (the basin check; the GPU tests also compare the rows' argmax)."""
+    gpath = os.path.join(GOLDEN, "c3sub5000_oracle.json")
+    ipath = os.path.join(GOLDEN, "c3sub5000_inputs.npz")
+    if not (os.path.exists(gpath) and os.path.exists(ipath)):
+        return None
+    with open(gpath) as fh:
+        gold = json.load(fh)
+    with np.load(ipath) as z:
+        X, a, Y, b = (torch.tensor(z[k], dtype=torch.float32, device=dev) for k in ("X", "a", "Y", "b"))
+    sv_ref = np.array(gold["gamma_sv"])
+    ctx = gwm.Context()
+    ctx.set_penalty(2, "features")
+    out = {"workload": f"seeded {X.shape[0]}+{Y.shape[0]} subsample, |x-x'| lifted to D=E={X.shape[1]} (oracle "
+                       f"landmark kPCA, 2048 landmarks), eps {gold['eps_start']}->{gold['eps_end']}, "
+                       f"{gold['n_outer']}x{gold['n_inner']}",
+           "oracle_loss_lift": gold["loss_lift"], "oracle_marginal_err": gold["marginal_error"]}
+    for prec in ("fp32", "bf16", "bf16x3"):
+        r = ctx.solve(X, a, Y, b, gold["eps_start"], gold["eps_end"], gold["n_outer"], gold["n_inner"], precision=prec)
+        sv = np.linalg.svd(r["gamma"].double().cpu().numpy(), compute_uv=False)
+        rel = abs(r["loss_lift"] - gold["loss_lift"]) / abs(gold["loss_lift"])
+        target = 1e-3 if prec == "bf16" else 1e-5
+        out[prec] = {"loss_lift": r["loss_lift"], "rel_loss_err": rel, "target_rel_loss_err": target,
+                     "target_met": rel <= target, "marginal_err": r["marginal_err"],
+                     "gamma_sv_rel_err": float(np.max(np.abs(sv - sv_ref)) / sv_ref.max())}
+        log(f"subsample parity {prec}: rel loss err {out[prec]['rel_loss_err']:.2e}, "
+            f"Err {r['marginal_err']:.2e} (oracle {gold['marginal_error']:.2e})")
+    return out
+
+
+def cpu_baseline(max_single_s: float) -> dict | None:
+    """The FP64 oracle as it stands (its compiled Sinkhorn loop, OpenMP over
+    rows, with NumPy for the materialised cost, the plan and the covariance)
+    on the seeded 5,000 + 5,000 subsample of the workload: one outer step of
+    Algorithm 1 with the workload's 100 symmetric Sinkhorn iterations, on all
+    host cores; then on one core, with as many iterations as fit about
+    max_single_s seconds."""
+    import platform
+
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import gw_oracle as O
+
+    ipath = os.path.join(GOLDEN, "c3sub5000_inputs.npz")
+    if not os.path.exists(ipath):
+        return None
+    with np.load(ipath) as z:
+        X, a, Y, b = (z[k].astype(np.float64) for k in ("X", "a", "Y", "b"))
+    a, b = a / a.sum(), b / b.sum()
+    X, Y = O.centre(X, a), O.centre(Y, b)
+    eps = 0.1
+
+    def run(iters):
+        t0 = time.perf_counter()
+        O.cnt_gw(a, b, X, Y, eps, eps, 1, iters, backend="c")
+        return time.perf_counter() - t0
+
+    log("cpu baseline: oracle on all cores, one outer step of 100 iterations")
+    t1 = run(1)
+    dt_all = run(100)
+    threads = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "openmp"), default=1)
+    per_iter_all = max((dt_all - t1) / 99, 1e-9)
+    fixed = max(t1 - per_iter_all, 0.0)
+    log(f"cpu baseline: 100 iterations in {dt_all:.1f} s on {threads} threads; now one thread")
+    with threadpool_limits(limits=1):
+        t1s = run(1)
+        fixed_s = min(fixed * 1.2 + 0.2, t1s)
+        per_iter_s = max(t1s - fixed_s, 1e-3)
+        iters_one = int(max(2, min(100, (max_single_s - fixed_s) / per_iter_s)))
+        dt_one = run(iters_one)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        model = platform.processor()
+    nm = float(X.shape[0]) * Y.shape[0]
+    return {"value": nm * 100 / dt_all, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"seeded {X.shape[0]}+{Y.shape[0]} subsample of the 200k workload (D=E={X.shape[1]} oracle "
+                      f"kPCA features): one outer step of Algorithm 1 at eps={eps} with 100 symmetric Sinkhorn "
+                      f"iterations, FP64, cost materialisation, plan and covariance included: {dt_all:.1f} s "
+                      f"({fixed:.1f} s of it outside the iterations)",
+            "iterations_only_entries_per_s": nm / per_iter_all,
+            "single_thread": {"value": nm * iters_one / dt_one, "iterations": iters_one, "seconds": dt_one},
+            "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
               "not built (the row-sharded design is described with the library)", file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
+
+    def remaining():
+        return args.budget_s - (time.perf_counter() - t_start)
+
     import torch
 
     import paper_2602_06658_amd as gwm
@@ -486,6 +741,18 @@ def main():
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(args, gwm, torch, dev)}), flush=True)
         return
+
+    peaks = None
+    try:
+        peaks = measure_peaks()
+        if peaks:
+            log(f"peaks: fma {peaks['fma_per_s']:.3e}/s, exp+sub {peaks['exp_sub_per_s']:.3e}/s, "
+                f"pass VALU mix {peaks['pass_valu_entries_per_s']:.3e} entries/s, MFMA bf16 "
+                f"{peaks['mfma_bf16_tflops']:.0f} TF/s, f32 {peaks['mfma_f32_tflops']:.1f} TF/s, clock "
+                f"{peaks['shader_clock_ghz']:.2f} GHz")
+    except Exception as e:  # a diagnostic; the headline does not depend on it
+        log(f"peaks probe failed: {e}")
+
     prob = config3_scale(n=args.n, lifted_dim=args.dim)
     n, m = prob.n, prob.m
     t = lambda v: torch.tensor(np.asarray(v, dtype=np.float32), device=dev)  # noqa: E731
@@ -519,6 +786,7 @@ def main():
         if args.save_features:
             np.savez(args.save_features, X=X.cpu().numpy(), Y=Y.cpu().numpy(), a=a.cpu().numpy(),
                      b=b.cpu().numpy())
+    log(f"workload ready: N=M={n}, D={args.dim}, lift {lift_s if lift_s is None else round(lift_s, 3)} s")
 
     if args.msgw:
         print(json.dumps({"msgw": msgw_bench(args, gwm, torch, X, a, Y, b, prob)}), flush=True)
@@ -529,34 +797,40 @@ def main():
 
     ctx = gwm.Context()
     ctx.set_penalty(2, "features")
+    prec = args.precision
+    head = stepwise_solve(ctx, torch, X, a, Y, b, prob, args, prec, args.warmup, args.steps,
+                          finish=not args.no_finish)
+    elapsed = head["elapsed_s"]
+    entries_per_step = float(n) * m * args.n_inner
+    value = entries_per_step * args.steps / elapsed
+    n_l, avg_ms = pass_figures(head["profile"])
+    res = head.get("result")
+    log(f"headline {prec}: {value:.3e} entries/s over {args.steps} steps ({elapsed:.1f} s); pass {avg_ms} ms "
+        f"x {n_l}" + (f"; loss {res['loss_lift']:.8g}, Err {res['marginal_err']:.2e}" if res else ""))
 
-    def solve(prec=args.precision, n_outer=args.n_outer):
-        return ctx.solve(X, a, Y, b, prob.eps_start, prob.eps_end if n_outer == args.n_outer else prob.eps_start,
-                         n_outer, args.n_inner, precision=prec)
-
-    for _ in range(args.warmup):
-        solve()
-    torch.cuda.synchronize()
-    ctx.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = None
-    for _ in range(args.steps):
-        res = solve()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile()
-    ctx.set_profiling(False)
-
-    entries_per_solve = float(n) * m * args.n_outer * args.n_inner
-    value = entries_per_solve * args.steps / elapsed
-    st = prof["pass_stab"]
-    avg_ms = st["ms"] / max(1, st["launches"])
     entries_per_launch = float(n) * m
-    achieved = entries_per_launch / (avg_ms * 1e-3) / 1e9
-    peak = alu_peak_entries_per_s() / 1e9
+    if prec == "fp32":
+        achieved = ALGO_FLOPS_PER_ENTRY * entries_per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["fp32"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_MFMA_TFLOPS["fp32"], "traffic": recorded_traffic(prec),
+                "per_unit": f"{ALGO_FLOPS_PER_ENTRY} algorithmic flops per entry (the D=64 feature dot), "
+                            f"{entries_per_launch:.0f} entries per launch",
+                "executed_mfma_tflops": MFMA_FLOPS_PER_ENTRY[prec] * entries_per_launch / (avg_ms * 1e-3) / 1e12}
+    else:
+        alu_peak = peaks["alu_model_entries_per_s"] if peaks else None
+        achieved = entries_per_launch / (avg_ms * 1e-3)
+        roof = {"bound": "alu", "achieved": achieved, "peak": alu_peak, "unit": "entries/s",
+                "frac": achieved / alu_peak if alu_peak else None, "traffic": recorded_traffic(prec),
+                "per_unit": "one exp2 and two FP32 adds per entry; rates from the peaks probe",
+                "mfma_frac": MFMA_FLOPS_PER_ENTRY[prec] * entries_per_launch / (avg_ms * 1e-3) / 1e12
+                / PEAK_MFMA_TFLOPS[prec]}
+    roof.update({"kernel": f"k_pass_stab ({prec} core), the stabilised Sinkhorn pass",
+                 "avg_launch_ms": avg_ms, "launches": n_l,
+                 "timing": "HIP events on the library's stream around every launch in the timed steps; "
+                           "mode-gated no-op launches (under 20 us) excluded"})
+    prof_ms = {k: v["ms"] for k, v in head["profile"].items() if isinstance(v, dict)}
     out = {
-        "metric": "GW cost entries/sec (N*M*Sinkhorn iters/s)",
+        "metric": "GW cost entries/sec (N·M·Sinkhorn iters/s) at N=M=200k; solves/s + p50/p99 latency",
         "value": value,
         "unit": "entries/s",
         "n_gpus": 1,
@@ -566,35 +840,81 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
-        "data": "synthetic",
-        "config": {"workload": f"gmm3d N=M={n}, |x-x'| penalty lifted to D=E={args.dim} "
-                               f"({args.landmarks} landmarks), eps 0.1->0.005, "
-                               f"{args.n_outer}x{args.n_inner} symmetric Sinkhorn",
-                   "global_batch": 1, "seq_len": n, "parallelism": "none"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gentry/s",
-                     "frac": achieved / peak, "traffic": recorded_traffic(),
-                     "kernel": "k_pass_stab (stabilised Sinkhorn pass)",
-                     "avg_launch_ms": avg_ms, "launches": st["launches"]},
-        "solve": {k: res[k] for k in ("loss_lift", "egw_objective", "kl", "marginal_err", "gamma_step",
-                                      "outer_done", "safe_iters")},
+        "dtype": prec,
+        "data": "synthetic: seeded 3-D Gaussian-mixture clouds standing in for the paper's shape datasets",
+        "config": {"workload": f"gmm3d N=M={n}, |x-x'| penalty lifted to D=E={args.dim} ({args.landmarks} "
+                               f"landmarks), eps {prob.eps_start}->{prob.eps_end} over {args.n_outer} outer "
+                               f"steps x {args.n_inner} symmetric Sinkhorn iterations",
+                   "step": f"one outer step of Algorithm 1 ({args.n_inner} Sinkhorn iterations, prologue, "
+                           f"covariance); timed outer steps {args.warmup}..{args.warmup + args.steps - 1}",
+                   "precision": f"{prec} feature contraction; log-sum-exp and sums in FP32; potentials FP32 "
+                                "(hi, lo) pairs updated in FP64 by the combine; FP64 Gamma reduction and "
+                                "final check"},
+        "roofline": roof,
+        "whole_solve": None if res is None else {
+            "seconds": head.get("whole_solve_s"),
+            "entries_per_s": (entries_per_step * args.n_outer / head["whole_solve_s"]
+                              if head.get("whole_solve_s") else None),
+            "loss_lift": res["loss_lift"], "egw_objective": res["egw_objective"], "kl": res["kl"],
+            "marginal_err": res["marginal_err"], "gamma_step": res["gamma_step"],
+            "outer_done": res["outer_done"], "safe_iters": res["safe_iters"]},
+        "profile_ms_timed_steps": prof_ms,
         "lift_seconds": lift_s,
-        "profile_ms": {k: v["ms"] for k, v in prof.items() if isinstance(v, dict)},
-        "mfma_bf16_tflops_in_pass": 2.0 * (args.dim + 16) * entries_per_launch / (avg_ms * 1e-3) / 1e12,
+        "peaks": peaks,
+        "skipped": [],
     }
-    if args.compare:
-        cmp = {}
-        for prec in ("fp32", "bf16x3"):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            solve(prec, 1)
-            torch.cuda.synchronize()
-            cmp[prec] = float(n) * m * args.n_inner / (time.perf_counter() - t1)
-        out["compare_entries_per_s_one_outer_step"] = cmp
-    if not args.no_serve:
-        out["serving"] = serve_bench(args, gwm, torch, dev)
+    one_step_s = elapsed / args.steps
+
+    def leg(name, estimate_s, fn):
+        if remaining() < estimate_s:
+            out["skipped"].append(f"{name}: needs about {estimate_s:.0f} s, {remaining():.0f} s of budget left")
+            log(f"skip {name}")
+            return None
+        try:
+            r = fn()
+            log(f"{name} done ({time.perf_counter() - t_start:.0f} s into the run)")
+            return r
+        except Exception as e:  # report, keep the line
+            out["skipped"].append(f"{name}: {type(e).__name__}: {e}")
+            log(f"{name} failed: {e}")
+            return None
+
+    if not args.no_forms and res is not None:
+        warm = {"gamma": res["gamma"], "f": res["f"], "g": res["g"]}
+        forms = {}
+        for p_ in ("fp32", "bf16", "bf16x3"):
+            est = one_step_s * (1.2 if p_ == "fp32" else 0.5) + 2
+            r = leg(f"form {p_}", est, lambda p_=p_: form_step(ctx, torch, X, a, Y, b, prob, args, p_, warm))
+            if r:
+                forms[p_] = r
+        out["forms_last_temperature"] = forms
+    if not args.no_parity:
+        out["parity_subsample"] = leg("subsample parity", 20, lambda: subsample_parity(gwm, torch, dev, args))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, args.cpu_iters)
+        out["cpu_baseline"] = leg("cpu baseline", args.cpu_seconds + 30, lambda: cpu_baseline(args.cpu_seconds))
+    if not args.no_whole_bf16 and prec != "bf16":
+        bf = out.get("forms_last_temperature", {}).get("bf16")
+        est = (bf["seconds"] * args.n_outer * 1.3 + 5) if bf else one_step_s * args.n_outer / 3
+
+        def whole_bf16():
+            w = stepwise_solve(ctx, torch, X, a, Y, b, prob, args, "bf16", 0, args.n_outer, finish=True)
+            r = w["result"]
+            nb, avg_b = pass_figures(w["profile"])
+            return {"seconds": w.get("whole_solve_s"),
+                    "entries_per_s": entries_per_step * args.n_outer / w["whole_solve_s"],
+                    "loss_lift": r["loss_lift"], "egw_objective": r["egw_objective"],
+                    "marginal_err": r["marginal_err"], "safe_iters": r["safe_iters"],
+                    "rel_loss_diff_vs_headline": (abs(r["loss_lift"] - res["loss_lift"]) / abs(res["loss_lift"])
+                                                  if res else None),
+                    "pass_avg_ms": avg_b, "pass_launches": nb,
+                    "pass_mfma_bf16_frac": MFMA_FLOPS_PER_ENTRY["bf16"] * entries_per_launch / (avg_b * 1e-3)
+                    / 1e12 / PEAK_MFMA_TFLOPS["bf16"],
+                    "pass_alu_model_frac": (entries_per_launch / (avg_b * 1e-3) / peaks["alu_model_entries_per_s"]
+                                            if peaks else None)}
+        out["whole_solve_bf16"] = leg("whole bf16 solve", est, whole_bf16)
+    if not args.no_serve:
+        out["serving"] = leg("serving", 150, lambda: serve_bench(args, gwm, torch, dev))
+    out["run_seconds"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
 
 

@@ -4,6 +4,10 @@ Every .hip and .cpp file under csrc/ is compiled to an object with
 ``--offload-arch=gfx950`` and packed-FP32 instructions disabled, then linked
 into ``paper_2602_06658_amd/libgwmi.so``.  Objects go to ``_build/`` beside
 this file; unchanged sources are not recompiled unless ``force``.
+
+``build_peaks`` compiles the instruction-rate microbenchmark
+(peaks/peaks.hip) into its own ``libgwpeaks.so``, which bench.py runs to
+derive the pass's roofline.
 """
 from __future__ import annotations
 
@@ -16,6 +20,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgwmi.so")
+PEAKS_SRC = os.path.join(HERE, "peaks", "peaks.hip")
+PEAKS_OUT = os.path.join(HERE, "libgwpeaks.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -90,5 +96,18 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
     return OUT
 
 
+def build_peaks(verbose: bool = True) -> str:
+    tmp = PEAKS_OUT + ".tmp"
+    cmd = [HIPCC] + COMMON + ["-shared", "-x", "hip", PEAKS_SRC, "-o", tmp, "-L/opt/rocm/lib", "-lamdhip64"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"peaks build failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, PEAKS_OUT)
+    if verbose:
+        print("built", PEAKS_OUT, file=sys.stderr)
+    return PEAKS_OUT
+
+
 if __name__ == "__main__":
     build(force="--force" in sys.argv)
+    build_peaks()
