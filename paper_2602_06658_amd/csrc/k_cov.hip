@@ -581,37 +581,42 @@ hipError_t launch_cov(int path, int prec, int d, const void* A, const void* B, c
 // Reduction of the covariance partials (fixed order) and Gamma in FP64.
 // ---------------------------------------------------------------------------
 
-constexpr int RED_ROWS = 64;
+// Rows per reduction block: the block keeps its rows' T_i in LDS as FP64,
+// 64 rows up to 64 columns (33 KB), fewer for wider payloads.
+__host__ __device__ inline int red_rows(int dw) { return dw <= 64 ? 64 : (dw <= 128 ? 32 : 16); }
 
+// Partials of every column tile summed in FP64 (T_i, r_i, rm_i), then the
+// block's share of Gamma = sum_i X_i T_i^T in FP64 from those FP64 sums.
 __global__ void __launch_bounds__(256) k_cov_reduce(const float* Tp, const float* rp, const float* rmp, int n_mt_c,
                                                     int tw, int64_t n, int64_t n_pad, const float* Xs, int dx,
                                                     const float* xs_norm, int dw, float* T, float* r, float* rm,
                                                     double* part) {
-    extern __shared__ float tsh[];  // RED_ROWS x (dw + 1)
+    extern __shared__ double tsh[];  // rows x (dw + 1)
     __shared__ double sred[256];
-    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
+    const int rows = red_rows(dw);
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
     double acc_r = 0.0, acc_nm = 0.0;
-    for (int u = threadIdx.x; u < RED_ROWS * dw; u += blockDim.x) {
+    for (int u = threadIdx.x; u < rows * dw; u += blockDim.x) {
         const int li = u / dw, e = u - li * dw;
         const int64_t i = r0 + li;
-        float s = 0.f;
+        double s = 0.0;
         if (i < n)
-            for (int c = 0; c < n_mt_c; ++c) s += Tp[((size_t)c * n_pad + i) * tw + e];
+            for (int c = 0; c < n_mt_c; ++c) s += (double)Tp[((size_t)c * n_pad + i) * tw + e];
         tsh[li * (dw + 1) + e] = s;
-        if (T && i < n) T[i * dw + e] = s;
+        if (T && i < n) T[i * dw + e] = (float)s;
     }
-    if (threadIdx.x < RED_ROWS) {
+    if (threadIdx.x < rows) {
         const int64_t i = r0 + threadIdx.x;
         if (i < n) {
-            float sr = 0.f, sm = 0.f;
+            double sr = 0.0, sm = 0.0;
             for (int c = 0; c < n_mt_c; ++c) {
-                sr += rp[(size_t)c * n_pad + i];
-                sm += rmp[(size_t)c * n_pad + i];
+                sr += (double)rp[(size_t)c * n_pad + i];
+                sm += (double)rmp[(size_t)c * n_pad + i];
             }
-            if (r) r[i] = sr;
-            if (rm) rm[i] = sm;
-            acc_r = (double)sr;
-            acc_nm = (double)sm * (double)xs_norm[i];
+            if (r) r[i] = (float)sr;
+            if (rm) rm[i] = (float)sm;
+            acc_r = sr;
+            acc_nm = sm * (double)xs_norm[i];
         }
     }
     __syncthreads();
@@ -620,10 +625,10 @@ __global__ void __launch_bounds__(256) k_cov_reduce(const float* Tp, const float
     for (int pidx = threadIdx.x; pidx < width; pidx += blockDim.x) {
         const int dd = pidx / dw, e = pidx - dd * dw;
         double s = 0.0;
-        for (int li = 0; li < RED_ROWS; ++li) {
+        for (int li = 0; li < rows; ++li) {
             const int64_t i = r0 + li;
             if (i >= n) break;
-            s += (double)Xs[i * dx + dd] * (double)tsh[li * (dw + 1) + e];
+            s += (double)Xs[i * dx + dd] * tsh[li * (dw + 1) + e];
         }
         out[pidx] = s;
     }
@@ -646,14 +651,16 @@ __global__ void __launch_bounds__(256) k_cov_reduce(const float* Tp, const float
 }
 
 size_t cov_reduce_part_doubles(int64_t n, int dx, int dw) {
-    return (size_t)((n + RED_ROWS - 1) / RED_ROWS) * (dx * dw + 2);
+    const int rows = red_rows(dw);
+    return (size_t)((n + rows - 1) / rows) * (dx * dw + 2);
 }
 
 hipError_t launch_cov_reduce(const CovOut& in, int n_mt_c, int64_t n, int64_t n_pad, const float* Xs, int dx,
                              const float* xs_norm, int dw, float* T, float* r, float* rm, double* part,
                              hipStream_t stream) {
-    const int nblk = (int)((n + RED_ROWS - 1) / RED_ROWS);
-    const size_t lds = (size_t)RED_ROWS * (dw + 1) * sizeof(float);
+    const int rows = red_rows(dw);
+    const int nblk = (int)((n + rows - 1) / rows);
+    const size_t lds = (size_t)rows * (dw + 1) * sizeof(double);
     hipLaunchKernelGGL(k_cov_reduce, dim3(nblk), dim3(256), lds, stream, in.Tp, in.rp, in.rmp, n_mt_c, in.tw, n,
                        n_pad, Xs, dx, xs_norm, dw, T, r, rm, part);
     return hipGetLastError();
@@ -710,7 +717,8 @@ __global__ void __launch_bounds__(256) k_gamma_norms(const double* gamma64, cons
 
 hipError_t launch_gamma_final(const double* part, int64_t n, int dx, int dw, const float* gamma_old, double* gamma64,
                               float* gamma32, double* scal, hipStream_t stream) {
-    const int nblk = (int)((n + RED_ROWS - 1) / RED_ROWS);
+    const int rows = red_rows(dw);
+    const int nblk = (int)((n + rows - 1) / rows);
     const int width = dx * dw;
     hipLaunchKernelGGL(k_gamma_sum, dim3((width + 2 + 63) / 64), dim3(256), 0, stream, part, nblk, width, gamma64,
                        gamma32, scal);
