@@ -194,6 +194,29 @@ gw_status gw_solve(gw_ctx* ctx,
                    const gw_params* params, const float* gamma0,
                    gw_result* out);
 
+/* gw_solve for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation):
+   the same solve, bit for bit, with every device buffer carved from a fixed
+   scratch array of 256 MiB per GPU that the library holds until the process
+   ends, so the call makes no hipMalloc, hipFree or other allocating call
+   (host bookkeeping uses the C++ heap).  Inputs, outputs and errors as
+   gw_solve, with these limits: both sides must use GW_PEN_SQEUCLID or
+   GW_PEN_FEATURES (lifting allocates; GW_EUNSUPPORTED otherwise);
+   adaptive_inner is not run (GW_EUNSUPPORTED); a problem whose buffers
+   exceed the array is refused with GW_ENOMEM before any work (square
+   problems up to about 159,000 points per side at D = 3, 67,000 at D = 32
+   and 29,000 at D = 64).
+   Profiling is not recorded.  Calls in one process are serialised (they
+   share the array and a host staging buffer), and the array is only in use
+   during a call (which waits for its results): its contents are left from
+   the previous call and nothing in it needs to start at zero.  Calls from
+   different processes use their own copies. */
+gw_status gw_solve_noalloc(gw_ctx* ctx,
+                           const float* x, int64_t n, int dx, const float* a,
+                           const float* y, int64_t m, int dy, const float* b,
+                           const gw_params* params, const float* gamma0,
+                           gw_result* out);
+
 /* ---- Stepwise solve: Algorithm 1 one outer step at a time ----
    The state of Algorithm 1 between outer steps is (f, g, Gamma_t, t, eps_t)
    (Algorithm 1; warm starts as in Appendix B.1).  These three calls keep it

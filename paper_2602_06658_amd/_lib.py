@@ -148,6 +148,10 @@ SIGNATURES = {
     "gw_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                 ctypes.POINTER(GwParams), ctypes.c_void_p, ctypes.POINTER(GwResult)]),
+    "gw_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.POINTER(GwParams), ctypes.c_void_p,
+                                        ctypes.POINTER(GwResult)]),
     "gw_solve_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.POINTER(GwParams), ctypes.c_void_p, ctypes.POINTER(GwResult)]),

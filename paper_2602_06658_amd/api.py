@@ -148,6 +148,28 @@ class Context:
                                       ctypes.byref(prm), _ptr(g0t), ctypes.byref(r)))
         return _result_dict(r, f, g, gamma)
 
+    def solve_noalloc(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
+                      precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, tol_gamma=0.0,
+                      anneal_final=False) -> dict:
+        """solve() through gw_solve_noalloc: the library allocates no device
+        memory (its buffers come from a fixed scratch array); the outputs are
+        allocated here, by torch."""
+        x, a, y, b = self._prep(x, a, y, b)
+        n, dx = x.shape
+        m, dy = y.shape
+        D, E = self.feature_dim(0, dx), self.feature_dim(1, dy)
+        f = torch.empty(n, dtype=torch.float32, device=x.device) if f0 is None else _dev_f32(f0, "f0").clone()
+        g = torch.empty(m, dtype=torch.float32, device=x.device) if g0 is None else _dev_f32(g0, "g0").clone()
+        gamma = torch.empty((D, E), dtype=torch.float32, device=x.device)
+        g0t = None if gamma0 is None else _dev_f32(gamma0, "gamma0")
+        prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode,
+                          f0 is not None and g0 is not None, tol_gamma, anneal_final, False)
+        r = L.GwResult()
+        r.f, r.g, r.gamma = f.data_ptr(), g.data_ptr(), gamma.data_ptr()
+        self._check(self.lib.gw_solve_noalloc(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
+                                              ctypes.byref(prm), _ptr(g0t), ctypes.byref(r)))
+        return _result_dict(r, f, g, gamma)
+
     def solve_begin(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
                     precision="fp32", mode="auto", gamma0=None, f0=None, g0=None, tol_gamma=0.0,
                     anneal_final=False, adaptive_inner=False):

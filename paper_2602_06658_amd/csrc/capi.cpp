@@ -5,11 +5,22 @@
 #include <new>
 
 #include "gw_grad.h"
+#include "gw_scratch.h"
 #include "runtime.h"
 
 using gwr::Ctx;
 using gwr::Status;
 
+
+namespace {
+// Readback staging of gw_solve_noalloc: 16 scalars, the moments of both
+// sides (2 + D^2 + D doubles each, D <= 256) and the control words.
+constexpr size_t NOALLOC_STAGE_DOUBLES = 16 + 2 * (2 + 256 * 256 + 256) + 8;
+double g_noalloc_stage[NOALLOC_STAGE_DOUBLES];
+// gw_solve_noalloc calls of this process share the scratch array and the
+// staging above, so they run one at a time.
+std::mutex g_noalloc_mu;
+}  // namespace
 
 static gw_status ret(gw_ctx* ctx, const Status& s) {
     if (ctx) ctx->c.err = s.good() ? std::string() : s.msg;
@@ -140,6 +151,59 @@ static gw_status solve_impl(gw_ctx* ctx, const float* x, int64_t n, int dx, cons
 gw_status gw_solve(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m, int dy,
                    const float* b, const gw_params* params, const float* gamma0, gw_result* out) {
     return solve_impl(ctx, x, n, dx, a, y, m, dy, b, params, gamma0, out, nullptr, nullptr, nullptr, nullptr, false);
+}
+
+gw_status gw_solve_noalloc(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
+                           int dy, const float* b, const gw_params* params, const float* gamma0, gw_result* out) {
+    if (!ctx) return GW_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    if (!out) return ret(ctx, gwr::fail(GW_EINVAL, "result is NULL"));
+    for (int s = 0; s < 2; ++s)
+        if (ctx->c.side[s].kind == GW_PEN_POWER)
+            return ret(ctx, gwr::fail(GW_EUNSUPPORTED,
+                                      "gw_solve_noalloc takes squared-norm or feature penalties (lifting allocates)"));
+    if (params && params->adaptive_inner)
+        return ret(ctx, gwr::fail(GW_EUNSUPPORTED, "gw_solve_noalloc does not run adaptive counts"));
+    if (hipSetDevice(ctx->c.device) != hipSuccess) return ret(ctx, gwr::fail(GW_EDEVICE, "hipSetDevice"));
+    Status st = gwr::validate_inputs(ctx->c, x, n, dx, a, y, m, dy, b, params, "n.");
+    if (!st.good()) return ret(ctx, st);
+    if (params->use_init_potentials && (!out->f || !out->g))
+        return ret(ctx, gwr::fail(GW_EINVAL, "warm start needs result->f and result->g"));
+    // this device's copy of the fixed scratch array: its address is looked
+    // up once per device, here rather than in gw_create so that a failure
+    // can only affect this entry point
+    if (gwr::scratch_init(ctx->c.device) != hipSuccess)
+        return ret(ctx, gwr::fail(GW_EDEVICE, "scratch array address unavailable on this device"));
+    void* scratch = gwr::scratch_ptr(ctx->c.device);
+    if (!scratch) return ret(ctx, gwr::fail(GW_EDEVICE, "scratch array address unavailable on this device"));
+    // every buffer the solve takes: its planned footprint, the validation
+    // and centring partials, the FP64 check's per-row sums, and alignment
+    const size_t plan = gwr::Solve::plan_bytes(ctx->c, n, dx, m, dy, *params);
+    if (plan == 0) return ret(ctx, gwr::fail(GW_EINVAL, "sizes rejected"));
+    const size_t need = plan + 8 * (gwk::centre_part_doubles(n, dx) + gwk::centre_part_doubles(m, dy) + dx + dy) +
+                        2 * (16 + 64 * 8) + 96 * 256;
+    if (need > gwr::SCRATCH_BYTES)
+        return ret(ctx, gwr::fail(GW_ENOMEM, "problem needs about " + std::to_string(need) +
+                                                 " bytes of scratch; gw_solve_noalloc holds " +
+                                                 std::to_string(gwr::SCRATCH_BYTES)));
+    std::lock_guard<std::mutex> glk(g_noalloc_mu);
+    gwr::Ctx local;
+    local.device = ctx->c.device;
+    local.stream = ctx->c.stream;
+    for (int s = 0; s < 2; ++s) local.side[s].kind = ctx->c.side[s].kind;
+    local.ws.use_arena(scratch, gwr::SCRATCH_BYTES);
+    local.set_host_stage(g_noalloc_stage, sizeof(g_noalloc_stage));
+    gwr::Solve solve(local, "n.");
+    const float* f0 = params->use_init_potentials ? out->f : nullptr;
+    const float* g0 = params->use_init_potentials ? out->g : nullptr;
+    st = solve.setup(x, n, dx, a, y, m, dy, b, *params, gamma0, f0, g0, local.side[0].kind, local.side[1].kind,
+                     local.stream);
+    while (st.good() && !solve.done()) st = solve.outer_step();
+    if (st.good()) st = solve.finish(out);
+    // finish waits for the stream; on an error path wait too, so that no
+    // kernel still reads the scratch array when the next call starts
+    (void)hipStreamSynchronize(local.stream);
+    return ret(ctx, st);
 }
 
 gw_status gw_solve_begin(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,

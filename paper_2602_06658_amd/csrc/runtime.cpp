@@ -34,6 +34,24 @@ void* Workspace::get(const std::string& name, size_t bytes, Status* st) {
     if (bytes == 0) bytes = 16;
     auto it = bufs_.find(name);
     if (it != bufs_.end() && it->second.bytes >= bytes) return it->second.p;
+    if (arena_) {
+        const size_t off = (arena_used_ + 255) / 256 * 256;
+        if (off > arena_bytes_ || bytes > arena_bytes_ - off) {
+            *st = fail(GW_ENOMEM, "scratch array of " + std::to_string(arena_bytes_) + " bytes exhausted at '" +
+                                      name + "' (" + std::to_string(bytes) + " more bytes after " +
+                                      std::to_string(off) + ")");
+            return nullptr;
+        }
+        void* p = arena_ + off;
+        if (it != bufs_.end()) {
+            total_ -= it->second.bytes;
+            bufs_.erase(it);
+        }
+        bufs_[name] = Buf{p, bytes, false};
+        total_ += bytes;
+        arena_used_ = off + bytes;
+        return p;
+    }
     size_t old = 0;
     if (it != bufs_.end()) old = it->second.bytes;
     if (limit_ && total_ - old + bytes > limit_) {
@@ -43,7 +61,7 @@ void* Workspace::get(const std::string& name, size_t bytes, Status* st) {
         return nullptr;
     }
     if (it != bufs_.end()) {
-        (void)hipFree(it->second.p);
+        if (it->second.owned) (void)hipFree(it->second.p);
         total_ -= it->second.bytes;
         bufs_.erase(it);
     }
@@ -59,15 +77,17 @@ void* Workspace::get(const std::string& name, size_t bytes, Status* st) {
 }
 
 void Workspace::release_all() {
-    for (auto& kv : bufs_) (void)hipFree(kv.second.p);
+    for (auto& kv : bufs_)
+        if (kv.second.owned) (void)hipFree(kv.second.p);
     bufs_.clear();
     total_ = 0;
+    arena_used_ = 0;
 }
 
 void Workspace::release_prefix(const std::string& prefix) {
     for (auto it = bufs_.begin(); it != bufs_.end();) {
         if (it->first.compare(0, prefix.size(), prefix) == 0) {
-            (void)hipFree(it->second.p);
+            if (it->second.owned) (void)hipFree(it->second.p);
             total_ -= it->second.bytes;
             it = bufs_.erase(it);
         } else {
@@ -81,6 +101,10 @@ void Workspace::release_prefix(const std::string& prefix) {
 // ---------------------------------------------------------------------------
 
 void* Ctx::host_stage(size_t bytes, Status* st) {
+    if (bytes > stage_bytes_ && !stage_owned_) {
+        *st = fail(GW_ENOMEM, "host staging of " + std::to_string(stage_bytes_) + " bytes is too small");
+        return nullptr;
+    }
     if (bytes > stage_bytes_) {
         if (stage_) (void)hipHostFree(stage_);
         stage_ = nullptr;
@@ -97,7 +121,7 @@ void* Ctx::host_stage(size_t bytes, Status* st) {
 
 Ctx::~Ctx() {
     stepped.reset();
-    if (stage_) (void)hipHostFree(stage_);
+    if (stage_ && stage_owned_) (void)hipHostFree(stage_);
 }
 
 hipEvent_t Profiler::take() {

@@ -55,15 +55,27 @@ class Workspace {
     size_t total() const { return total_; }
     size_t limit() const { return limit_; }
     void set_limit(size_t l) { limit_ = l; }
+    // Arena mode: buffers are carved from the caller's [base, base + bytes)
+    // in request order (256-byte aligned) instead of allocated, and never
+    // freed; get() fails with GW_ENOMEM when the arena is exhausted.
+    void use_arena(void* base, size_t bytes) {
+        arena_ = (char*)base;
+        arena_bytes_ = bytes;
+        arena_used_ = 0;
+    }
+    size_t arena_used() const { return arena_used_; }
 
    private:
     struct Buf {
         void* p = nullptr;
         size_t bytes = 0;
+        bool owned = true;
     };
     std::map<std::string, Buf> bufs_;
     size_t total_ = 0;
     size_t limit_ = 0;
+    char* arena_ = nullptr;
+    size_t arena_bytes_ = 0, arena_used_ = 0;
 };
 
 // Frozen landmark kernel PCA of one side (GW_PEN_POWER).
@@ -136,11 +148,19 @@ struct Ctx {
     // Pinned host staging for result readback, grown on demand; bytes = 0
     // returns the current buffer.
     void* host_stage(size_t bytes, Status* st);
+    // Use the caller's host buffer for readback instead (never grown or
+    // freed; a request beyond it fails).
+    void set_host_stage(void* p, size_t bytes) {
+        stage_ = p;
+        stage_bytes_ = bytes;
+        stage_owned_ = false;
+    }
     ~Ctx();
 
    private:
     void* stage_ = nullptr;
     size_t stage_bytes_ = 0;
+    bool stage_owned_ = true;
 };
 
 int feature_dim(const SideCfg& s, int d);
