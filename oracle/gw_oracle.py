@@ -678,6 +678,39 @@ def sgw_grad_positions(a, b, x, y, eps, tol=1e-13):
     return gx - 0.5 * (sx + tx), gy - 0.5 * (sy + ty)
 
 
+def sgw_grad_positions_lifted(a, b, x, y, eps, lmx: Landmarks, lmy: Landmarks, tol=1e-13):
+    """Position gradient of the Sinkhorn-GW divergence for a penalty lifted
+    by frozen landmark maps (|x - x'|^p through kernel PCA, Section 5,
+    Algorithm 4 and Algorithm 13): alpha's points are embedded by Pi_x and
+    beta's by Pi_y in every term, so GW_eps(alpha, alpha) compares
+    Pi_x(x) with itself and GW_eps(beta, beta) compares Pi_y(y) with itself.
+    Each envelope gradient (Appendix B.6) is taken with respect to the
+    re-centred features and chained through the centring and the frozen
+    map's Jacobian (Algorithm 12).  Returns (grad_x, grad_y)."""
+    def parts(p, P, lmP, q, Q, lmQ):
+        PP, QQ = landmark_features(P, p, lmP), landmark_features(Q, q, lmQ)
+        gam, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps, tol=tol, sink_tol=tol / 10)
+        gs = chain_centre(grad_features(PP, QQ, p, q, pi, gam), p)
+        gt = chain_centre(grad_features_target(PP, QQ, p, q, pi, gam), q)
+        return (np.einsum("nd,ndk->nk", gs, kernel_proj_jacobian(P, lmP)),
+                np.einsum("nd,ndk->nk", gt, kernel_proj_jacobian(Q, lmQ)))
+
+    gx, gy = parts(a, x, lmx, b, y, lmy)
+    sx, tx = parts(a, x, lmx, a, x, lmx)
+    sy, ty = parts(b, y, lmy, b, y, lmy)
+    return gx - 0.5 * (sx + tx), gy - 0.5 * (sy + ty)
+
+
+def sgw_value_converged_lifted(a, b, x, y, eps, lmx: Landmarks, lmy: Landmarks, tol=1e-13) -> float:
+    """SGW_eps of the measures embedded by the frozen maps Pi_x and Pi_y
+    (as in sgw_grad_positions_lifted), every EGW problem converged at eps."""
+    def one(p, P, lmP, q, Q, lmQ):
+        PP, QQ = landmark_features(P, p, lmP), landmark_features(Q, q, lmQ)
+        _, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps, tol=tol, sink_tol=tol / 10)
+        return egw_objective(PP, QQ, p, q, pi, eps)
+    return one(a, x, lmx, b, y, lmy) - 0.5 * (one(a, x, lmx, a, x, lmx) + one(b, y, lmy, b, y, lmy))
+
+
 def sgw_value_converged(a, b, x, y, eps, tol=1e-13) -> float:
     """SGW_eps with every EGW problem solved by cnt_gw_converged at eps."""
     def one(p, P, q, Q):
@@ -704,6 +737,27 @@ def sgw_barycenter(a, b, x, y, z0, w, lam, step, n_steps, eps, tol=1e-13):
             break
         gzx, _ = sgw_grad_positions(w, a, z, x, eps, tol)
         gzy, _ = sgw_grad_positions(w, b, z, y, eps, tol)
+        z = z - step / w[:, None] * ((1 - lam) * gzx + lam * gzy)
+    return z, obj
+
+
+def sgw_barycenter_lifted(a, b, x, y, z0, w, lam, step, n_steps, eps, lmz: Landmarks, lma: Landmarks,
+                          lmb: Landmarks, tol=1e-13):
+    """The barycentre flow of sgw_barycenter for a penalty lifted by frozen
+    landmark maps: z is embedded by Pi_z (its landmark points stay where
+    they were fitted while z moves), alpha by Pi_a and beta by Pi_b, in every
+    term (sgw_grad_positions_lifted).  Returns z after n_steps and the
+    objective before each step and after the last."""
+    z = np.array(z0, np.float64)
+    w = np.asarray(w, np.float64)
+    obj = []
+    for s in range(n_steps + 1):
+        obj.append((1 - lam) * sgw_value_converged_lifted(w, a, z, x, eps, lmz, lma, tol)
+                   + lam * sgw_value_converged_lifted(w, b, z, y, eps, lmz, lmb, tol))
+        if s == n_steps:
+            break
+        gzx, _ = sgw_grad_positions_lifted(w, a, z, x, eps, lmz, lma, tol)
+        gzy, _ = sgw_grad_positions_lifted(w, b, z, y, eps, lmz, lmb, tol)
         z = z - step / w[:, None] * ((1 - lam) * gzx + lam * gzy)
     return z, obj
 

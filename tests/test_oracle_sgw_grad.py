@@ -53,3 +53,70 @@ def test_gradient_vanishes_between_isometric_measures():
     scale = np.abs(O.grad_positions_sqeuclid(X, Y, a, b, pi, gam)).max()
     assert scale > 1e-2
     assert np.abs(gx).max() < 1e-8 * scale and np.abs(gy).max() < 1e-8 * scale
+
+
+# |x - x'| lifted by frozen landmark maps (Algorithm 4 and Algorithm 13):
+# alpha is embedded by Pi_x and beta by Pi_y in every term of the divergence
+
+
+def _lifted_case(rng, n, m, p=1.0, dim=4):
+    x, a = _measure(rng, n, 2)
+    y, b = _measure(rng, m, 2)
+    lmx = O.fit_landmarks(x[: n - 2], p, dim)
+    lmy = O.fit_landmarks(y[: m - 2], p, dim)
+    return x, a, y, b, lmx, lmy
+
+
+def test_lifted_gradient_matches_finite_differences():
+    rng = np.random.default_rng(42)
+    x, a, y, b, lmx, lmy = _lifted_case(rng, 9, 8)
+    gx, gy = O.sgw_grad_positions_lifted(a, b, x, y, EPS, lmx, lmy)
+    h = 1e-5
+    for _ in range(2):
+        dx = rng.standard_normal(x.shape)
+        dx /= np.linalg.norm(dx)
+        fd = (O.sgw_value_converged_lifted(a, b, x + h * dx, y, EPS, lmx, lmy)
+              - O.sgw_value_converged_lifted(a, b, x - h * dx, y, EPS, lmx, lmy)) / (2 * h)
+        assert abs(fd - np.sum(gx * dx)) < 1e-6 * np.abs(gx).sum()
+        dy = rng.standard_normal(y.shape)
+        dy /= np.linalg.norm(dy)
+        fd = (O.sgw_value_converged_lifted(a, b, x, y + h * dy, EPS, lmx, lmy)
+              - O.sgw_value_converged_lifted(a, b, x, y - h * dy, EPS, lmx, lmy)) / (2 * h)
+        assert abs(fd - np.sum(gy * dy)) < 1e-6 * np.abs(gy).sum()
+
+
+def test_lifted_gradient_of_the_linear_kernel_is_the_squared_norm_gradient():
+    # p = 2 with D = d: the landmark kernel is linear and the map an isometry
+    # of the plane onto its principal axes, so the lifted divergence is the
+    # squared-norm one and so is its gradient
+    rng = np.random.default_rng(43)
+    x, a, y, b, lmx, lmy = _lifted_case(rng, 9, 8, p=2.0, dim=2)
+    gx, gy = O.sgw_grad_positions_lifted(a, b, x, y, EPS, lmx, lmy)
+    hx, hy = O.sgw_grad_positions(a, b, x, y, EPS)
+    assert np.abs(gx - hx).max() < 1e-9 * np.abs(hx).max()
+    assert np.abs(gy - hy).max() < 1e-9 * np.abs(hy).max()
+
+
+def test_lifted_gradient_vanishes_between_isometric_measures():
+    # y is a rigid motion of x (permuted) and beta's landmarks are the images
+    # of alpha's in the same order: both maps see the same landmark kernel,
+    # so the embedded measures coincide and the pair is a minimum
+    rng = np.random.default_rng(44)
+    x, a = _measure(rng, 10, 2)
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    perm = rng.permutation(10)
+    y = (x @ R.T + np.array([0.3, -1.2]))[perm]
+    b = a[perm]
+    lm_idx = np.arange(8)
+    lmx = O.fit_landmarks(x[lm_idx], 1.0, 4)
+    inv = np.argsort(perm)
+    lmy = O.fit_landmarks(y[inv[lm_idx]], 1.0, 4)
+    gx, gy = O.sgw_grad_positions_lifted(a, b, x, y, EPS, lmx, lmy)
+    X, Y = O.landmark_features(x, a, lmx), O.landmark_features(y, b, lmy)
+    gam, pi, _, _ = O.cnt_gw_converged(a, b, X, Y, EPS)
+    pair = np.einsum("nd,ndk->nk", O.chain_centre(O.grad_features(X, Y, a, b, pi, gam), a),
+                     O.kernel_proj_jacobian(x, lmx))
+    scale = np.abs(pair).max()
+    assert scale > 1e-2
+    assert np.abs(gx).max() < 1e-7 * scale and np.abs(gy).max() < 1e-7 * scale
