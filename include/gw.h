@@ -280,10 +280,14 @@ gw_status gw_sgw(gw_ctx* ctx,
    gradients of Appendix B.6): the three solves of gw_sgw on the raw points,
    then grad_x = dGW(x, y)/dx - (dGW(x, x)/dx_source + dGW(x, x)/dx_target) / 2
    and the same for y (device, caller allocated, n x dx and m x dy).  The
-   envelope gradient is exact at converged solves.  Both sides must use the
-   same GW_PEN_SQEUCLID or GW_PEN_FEATURES penalty (GW_EUNSUPPORTED
-   otherwise); weight gradients are not provided.  Other inputs, outputs and
-   errors as gw_sgw. */
+   envelope gradient is exact at converged solves.  Each measure keeps its
+   side's penalty in every term: with GW_PEN_POWER the pair solve fits the
+   landmark maps (source on x, target on y, or keeps maps fitted before), the
+   self term of x uses x's frozen map on both of its sides and that of y
+   uses y's, and every gradient chains through its side's frozen map
+   (Algorithm 12 with Algorithm 13), as gw_sgw embeds the three problems.
+   Weight gradients are not provided.  Other inputs, outputs and errors as
+   gw_sgw. */
 gw_status gw_sgw_grad(gw_ctx* ctx,
                       const float* x, int64_t n, int dx, const float* a,
                       const float* y, int64_t m, int dy, const float* b,
@@ -299,9 +303,16 @@ gw_status gw_sgw_grad(gw_ctx* ctx,
    takes the divergence's position gradient (gw_sgw_grad) and moves
    z_i -= step / w_i * gradient_i; GW_eps(alpha, alpha) and GW_eps(beta, beta)
    are solved once.  objective (host, n_steps + 1 values, nullable) receives
-   the objective before each step and after the last.  Same penalty
-   restriction and errors as gw_sgw_grad; GW_EINVAL for lambda outside
-   [0, 1], step < 0 or n_steps outside [0, 100000]. */
+   the objective before each step and after the last.  Penalties: the same
+   GW_PEN_SQEUCLID or GW_PEN_FEATURES on both sides, or GW_PEN_POWER on both
+   sides, where z is embedded by a landmark map with side 0's settings
+   fitted on z as passed in (its landmark points stay there while z moves),
+   and alpha and beta by maps with side 1's settings fitted on x and on y
+   (landmark seeds s and s + 1, or side 1's explicit indices into both); all
+   solves then run on the embedded features and z's gradients chain through
+   its frozen map (GW_EUNSUPPORTED for other combinations).  Errors as
+   gw_sgw_grad; GW_EINVAL for lambda outside [0, 1], step < 0 or n_steps
+   outside [0, 100000]. */
 gw_status gw_sgw_barycenter(gw_ctx* ctx,
                             const float* x, int64_t n, const float* a,
                             const float* y, int64_t m, const float* b, int d,

@@ -5,10 +5,12 @@
 #include <new>
 
 #include "gw_grad.h"
+#include "gw_lift.h"
 #include "gw_scratch.h"
 #include "runtime.h"
 
 using gwr::Ctx;
+using gwr::hip_fail;
 using gwr::Status;
 
 
@@ -313,10 +315,6 @@ gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const floa
     if (!st.good()) return ret(ctx, st);
     if (params->use_init_potentials) return ret(ctx, gwr::fail(GW_EINVAL, "the divergence starts from zero potentials"));
     gwr::Ctx& c = ctx->c;
-    const int kind = c.side[0].kind;
-    if (c.side[1].kind != kind || (kind != GW_PEN_SQEUCLID && kind != GW_PEN_FEATURES))
-        return ret(ctx, gwr::fail(GW_EUNSUPPORTED,
-                                  "the divergence's gradient needs the same squared-norm or feature penalty on both sides"));
     float* gxs = c.ws.get_t<float>("sgw.gxs", (size_t)n * dx, &st);
     float* gxt = c.ws.get_t<float>("sgw.gxt", (size_t)n * dx, &st);
     float* gys = c.ws.get_t<float>("sgw.gys", (size_t)m * dy, &st);
@@ -325,15 +323,25 @@ gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const floa
     auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
                    const float* wq, gw_result& r, float* gP, float* gQ) -> Status {
         gwr::Solve solve(c, "s.");
-        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, kind, kind, c.stream));
+        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, c.side[0].kind,
+                           c.side[1].kind, c.stream));
         while (!solve.done()) GW_TRY(solve.outer_step());
         GW_TRY(solve.finish(&r));
         return solve.gradients(gP, nullptr, gQ, nullptr);
     };
+    // each measure keeps its own side's penalty in every term: the pair
+    // solve fits the landmark maps of |x - x'|^p (source on x, target on y),
+    // and the self terms use that one map on both of their sides
     gw_result rxy{}, rxx{}, ryy{};
     st = run(x, n, dx, a, y, m, dy, b, rxy, grad_x, grad_y);
-    if (st.good()) st = run(x, n, dx, a, x, n, dx, a, rxx, gxs, gxt);
-    if (st.good()) st = run(y, m, dy, b, y, m, dy, b, ryy, gys, gyt);
+    if (st.good()) {
+        gwr::SideShare share(c, 0, 1);
+        st = run(x, n, dx, a, x, n, dx, a, rxx, gxs, gxt);
+    }
+    if (st.good()) {
+        gwr::SideShare share(c, 1, 0);
+        st = run(y, m, dy, b, y, m, dy, b, ryy, gys, gyt);
+    }
     if (!st.good()) return ret(ctx, st);
     if (gwk::launch_sub_half_sum(grad_x, gxs, gxt, n * dx, c.stream) != hipSuccess ||
         gwk::launch_sub_half_sum(grad_y, gys, gyt, m * dy, c.stream) != hipSuccess ||
@@ -347,6 +355,88 @@ gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const floa
     out->dim_x = rxy.dim_x;
     out->dim_y = rxy.dim_y;
     return ret(ctx, Status::ok());
+}
+
+// Barycentre flow for |x - x'|^p lifted by frozen landmark maps: z is
+// embedded by a map with side 0's settings fitted on z as given (its
+// landmark points stay there while z moves), alpha and beta by maps with
+// side 1's settings fitted on x and on y (seeds s and s + 1 unless side 1
+// has explicit indices, which then index both).  Every solve runs on the
+// embedded features; z's feature gradients chain through its map's
+// Jacobian (Algorithm 12 with Algorithm 13).
+static Status bary_lifted(gwr::Ctx& c, const float* x, int64_t n, const float* a, const float* y, int64_t m,
+                          const float* b, int d, float* z, int64_t k, const float* w, double lambda, double step,
+                          int n_steps, const gw_params* params, double* objective) {
+    gwr::SideCfg cz = c.side[0], ca = c.side[1], cb = c.side[1];
+    cz.lm = gwr::Landmarks();
+    ca.lm = gwr::Landmarks();
+    cb.lm = gwr::Landmarks();
+    if (cb.explicit_idx.empty()) cb.seed = ca.seed + 1;
+    struct FreeMaps {
+        gwr::SideCfg* s[3];
+        ~FreeMaps() {
+            for (gwr::SideCfg* p : s) gwr::free_landmarks(p->lm);
+        }
+    } maps{{&cz, &ca, &cb}};
+    const int Dz = cz.lifted_dim, Da = ca.lifted_dim;
+    auto pad = [](int64_t v) { return (v + 31) / 32 * 32; };
+    Status st;
+    float* Zf = c.ws.get_t<float>("bc.Zf", (size_t)pad(k) * Dz, &st);
+    float* Xa = c.ws.get_t<float>("bc.Xa", (size_t)pad(n) * Da, &st);
+    float* Xb = c.ws.get_t<float>("bc.Xb", (size_t)pad(m) * Da, &st);
+    float* gf[4];
+    float* gp[4];
+    for (int q = 0; q < 4; ++q) {
+        gf[q] = c.ws.get_t<float>("bc.gf" + std::to_string(q), (size_t)k * Dz, &st);
+        gp[q] = c.ws.get_t<float>("bc.gp" + std::to_string(q), (size_t)k * d, &st);
+    }
+    if (!st.good()) return st;
+    // lift with a given side configuration in slot 0; the map fitted on the
+    // first lift stays in cfg
+    auto lift_with = [&](gwr::SideCfg& cfg, const float* P, int64_t np, const float* wp, float* out) -> Status {
+        gwr::SideCfg saved = std::move(c.side[0]);
+        c.side[0] = std::move(cfg);
+        Status s = gwr::lift_side(c, 0, P, np, d, wp, out, pad(np), "bc.");
+        cfg = std::move(c.side[0]);
+        c.side[0] = std::move(saved);
+        return s;
+    };
+    GW_TRY(lift_with(ca, x, n, a, Xa));
+    GW_TRY(lift_with(cb, y, m, b, Xb));
+    auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
+                   const float* wq, double* egw, float* gP, float* gQ) -> Status {
+        gwr::FeatureSides fs(c);
+        gwr::Solve solve(c, "s.");
+        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, GW_PEN_FEATURES,
+                           GW_PEN_FEATURES, c.stream));
+        while (!solve.done()) GW_TRY(solve.outer_step());
+        gw_result r{};
+        GW_TRY(solve.finish(&r));
+        *egw = r.egw_objective;
+        if (gP || gQ) GW_TRY(solve.gradients(gP, nullptr, gQ, nullptr));
+        return Status::ok();
+    };
+    double eaa = 0.0, ebb = 0.0;
+    GW_TRY(run(Xa, n, Da, a, Xa, n, Da, a, &eaa, nullptr, nullptr));
+    GW_TRY(run(Xb, m, Da, b, Xb, m, Da, b, &ebb, nullptr, nullptr));
+    for (int s = 0; s <= n_steps; ++s) {
+        const bool last = s == n_steps;
+        GW_TRY(lift_with(cz, z, k, w, Zf));
+        double ezx = 0.0, ezy = 0.0, ezz = 0.0;
+        GW_TRY(run(Zf, k, Dz, w, Xa, n, Da, a, &ezx, last ? nullptr : gf[0], nullptr));
+        GW_TRY(run(Zf, k, Dz, w, Xb, m, Da, b, &ezy, last ? nullptr : gf[1], nullptr));
+        GW_TRY(run(Zf, k, Dz, w, Zf, k, Dz, w, &ezz, last ? nullptr : gf[2], last ? nullptr : gf[3]));
+        if (objective)
+            objective[s] = (1.0 - lambda) * (ezx - 0.5 * (ezz + eaa)) + lambda * (ezy - 0.5 * (ezz + ebb));
+        if (last) break;
+        const gwr::Landmarks& lm = cz.lm;
+        for (int q = 0; q < 4; ++q)
+            GW_HIP(gwk::launch_nystrom_jt(z, k, lm.d_in, lm.pts, lm.n_l, lm.W, lm.dim, (float)cz.p, gf[q], gp[q],
+                                          c.stream));
+        GW_HIP(gwk::launch_bary_step(z, k, d, w, gp[0], gp[1], gp[2], gp[3], (float)lambda, (float)step, c.stream));
+    }
+    GW_HIP(hipStreamSynchronize(c.stream));
+    return Status::ok();
 }
 
 gw_status gw_sgw_barycenter(gw_ctx* ctx, const float* x, int64_t n, const float* a, const float* y, int64_t m,
@@ -366,9 +456,11 @@ gw_status gw_sgw_barycenter(gw_ctx* ctx, const float* x, int64_t n, const float*
     if (params->use_init_potentials) return ret(ctx, gwr::fail(GW_EINVAL, "the divergence starts from zero potentials"));
     gwr::Ctx& c = ctx->c;
     const int kind = c.side[0].kind;
+    if (kind == GW_PEN_POWER && c.side[1].kind == GW_PEN_POWER)
+        return ret(ctx, bary_lifted(c, x, n, a, y, m, b, d, z, k, w, lambda, step, n_steps, params, objective));
     if (c.side[1].kind != kind || (kind != GW_PEN_SQEUCLID && kind != GW_PEN_FEATURES))
         return ret(ctx, gwr::fail(GW_EUNSUPPORTED,
-                                  "the barycentre flow needs the same squared-norm or feature penalty on both sides"));
+                                  "the barycentre flow needs the same penalty kind on both sides"));
     float* g1 = c.ws.get_t<float>("bc.g1", (size_t)k * d, &st);
     float* g2 = c.ws.get_t<float>("bc.g2", (size_t)k * d, &st);
     float* gs = c.ws.get_t<float>("bc.gs", (size_t)k * d, &st);

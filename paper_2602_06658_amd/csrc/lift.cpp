@@ -22,6 +22,8 @@ static void free_lm(Landmarks& lm) {
     lm = Landmarks();
 }
 
+void free_landmarks(Landmarks& lm) { free_lm(lm); }
+
 void release_landmarks(Ctx& c) {
     for (int s = 0; s < 2; ++s) free_lm(c.side[s].lm);
     if (c.rocblas) {

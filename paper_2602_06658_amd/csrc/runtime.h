@@ -308,6 +308,8 @@ struct gw_ctx {
 
 namespace gwr {
 void release_landmarks(Ctx& c);
+// Free one landmark map's device data and mark it unfitted.
+void free_landmarks(Landmarks& lm);
 Status lift_nystrom(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
                     const std::string& tag);
 }  // namespace gwr
@@ -317,6 +319,22 @@ std::vector<int64_t> seeded_landmarks(int64_t n, int nl, uint64_t seed);
 }  // namespace gwr
 
 namespace gwr {
+// One side's penalty (with its fitted landmark map) used on the other side
+// too, for the self terms GW(alpha, alpha) and GW(beta, beta) of the
+// divergence; restored on every exit path.  The copy shares the fitted
+// landmark data, which only release_landmarks and a refit free, and a
+// fitted copy is never refitted.
+struct SideShare {
+    Ctx& c;
+    int dst;
+    SideCfg saved;
+    SideShare(Ctx& ctx, int src, int dst_) : c(ctx), dst(dst_) {
+        saved = std::move(c.side[dst]);
+        c.side[dst] = c.side[src];
+    }
+    ~SideShare() { c.side[dst] = std::move(saved); }
+};
+
 // The context's penalties replaced by "features" for solves that run on
 // features lifted beforehand; restored on every exit path.  (SideCfg holds
 // plain handles, so moving it out and back leaves fitted landmarks alone.)

@@ -61,10 +61,27 @@ def test_sgw_gradient_vanishes_between_isometric_measures(gw):
     assert res["grad_y"].abs().max().item() <= 1e-3 * scale
 
 
-def test_sgw_gradient_rejects_power_penalty(gw):
-    rng = np.random.default_rng(52)
-    x, a = _measure(rng, 30, 2)
+def test_lifted_sgw_gradient_matches_oracle(gw):
+    # |x - x'| lifted to D = 4 by landmark kernel PCA on the first points of
+    # each measure (the same indices on both sides of the comparison; the
+    # eigenvectors' signs may differ, which leaves the objective and the
+    # position gradients unchanged)
+    rng = np.random.default_rng(53)
+    x, a = _measure(rng, 40, 2)
+    y, b = _measure(rng, 35, 2)
+    ix, iy = np.arange(30), np.arange(28)
     ctx = gw.Context()
-    ctx.set_penalty(2, "power", p=1.0, lifted_dim=4, n_landmarks=16)
-    with pytest.raises(gw.GWError):
-        ctx.sgw_grad(dev(x), dev(a), dev(x), dev(a), EPS, EPS, 2, 5)
+    for side, idx in ((0, ix), (1, iy)):
+        ctx.set_penalty(side, "power", p=1.0, lifted_dim=4, n_landmarks=len(idx))
+        ctx.set_landmarks(side, idx)
+    print("lifted sgw grad n=40 m=35 D=4", flush=True)
+    res = ctx.sgw_grad(dev(x), dev(a), dev(y), dev(b), EPS, EPS, 40, 400)
+    lmx, lmy = O.fit_landmarks(x[ix], 1.0, 4), O.fit_landmarks(y[iy], 1.0, 4)
+    gx_ref, gy_ref = O.sgw_grad_positions_lifted(a, b, x, y, EPS, lmx, lmy)
+    gx, gy = res["grad_x"].cpu().numpy(), res["grad_y"].cpu().numpy()
+    ex = np.abs(gx - gx_ref).max() / np.abs(gx_ref).max()
+    ey = np.abs(gy - gy_ref).max() / np.abs(gy_ref).max()
+    ref_val = O.sgw_value_converged_lifted(a, b, x, y, EPS, lmx, lmy)
+    print("lifted errors", ex, ey, "sgw", res["sgw"], "oracle", ref_val, "err", res["marginal_err"])
+    assert ex <= 1e-4 and ey <= 1e-4
+    assert abs(res["sgw"] - ref_val) <= 1e-4 * abs(res["gw_xy"])
