@@ -731,8 +731,8 @@ hipError_t launch_gamma_final(const double* part, int64_t n, int dx, int dw, con
 // FP64 check: s_ij = sum_k A_ik B_jk evaluated exactly in FP64 from the
 // packed operands (the coupling the passes iterate), pi = 2^s.  One sweep
 // over the entries gives the row sums, the row KL terms and the column sums:
-// each work-group takes a CKM x CKM macro tile and writes per-tile partials,
-// which a second kernel adds up in tile order.
+// each work-group takes a span x span macro tile and writes per-tile
+// partials, which a second kernel adds up in tile order.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ float pack_elem(const void* pack, int prec, int units, int row, int k) {
@@ -744,13 +744,22 @@ __device__ __forceinline__ float pack_elem(const void* pack, int prec, int units
 // (K = 80 at D = 64 in two) decoded to float in LDS; each thread owns a
 // 4 x 4 block of entries (rows 4 ty + u, columns 4 tx + v).  The reduction
 // scratch reuses the operand tiles' LDS.
-constexpr int CK_T = 64, CK_KB = 40, CKM = 2048, CK_SUB = CKM / CK_T;
+constexpr int CK_T = 64, CK_KB = 40, CKM = 2048;
 
-int check_tiles(int64_t len) { return (int)((len + CKM - 1) / CKM); }
+// The macro tile's side: CKM, halved (down to one 64 x 64 sub-tile) while the
+// grid would have fewer than 512 work-groups, so that problems of a few
+// thousand points still spread over the CUs (the partials grow as the tile
+// shrinks, so large problems keep the full tile).
+int check_span(int64_t n, int64_t m) {
+    int s = CKM;
+    while (s > CK_T && ((n + s - 1) / s) * ((m + s - 1) / s) < 512) s >>= 1;
+    return s;
+}
 
 __global__ void __launch_bounds__(256) k_check64_tiles(int prec, int units, int K, const void* A, const void* B,
-                                                       int64_t n, int64_t m, const float* la2, const float* lb2,
-                                                       double* rpart, double* klpart, double* cpart) {
+                                                       int64_t n, int64_t m, int span, const float* la2,
+                                                       const float* lb2, double* rpart, double* klpart,
+                                                       double* cpart) {
     constexpr int TILE_FLOATS = CK_T * (CK_KB + 1);
     static_assert(2 * TILE_FLOATS * sizeof(float) >= 2 * 16 * CK_T * sizeof(double), "row scratch fits");
     static_assert(TILE_FLOATS * sizeof(float) >= 16 * CK_T * sizeof(double), "column scratch fits");
@@ -764,9 +773,10 @@ __global__ void __launch_bounds__(256) k_check64_tiles(int prec, int units, int 
     double(*redr)[16][CK_T] = reinterpret_cast<double(*)[16][CK_T]>(tiles_mem);
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int rt = blockIdx.y, ct = blockIdx.x;
-    const int64_t R0 = (int64_t)rt * CKM, C0 = (int64_t)ct * CKM;
-    for (int j = tid; j < CKM; j += 256) colacc[j] = 0.0;
-    for (int rs = 0; rs < CK_SUB && R0 + rs * CK_T < n; ++rs) {
+    const int64_t R0 = (int64_t)rt * span, C0 = (int64_t)ct * span;
+    const int n_sub = span / CK_T;
+    for (int j = tid; j < span; j += 256) colacc[j] = 0.0;
+    for (int rs = 0; rs < n_sub && R0 + rs * CK_T < n; ++rs) {
         const int64_t r0 = R0 + rs * CK_T;
         double rsum[4] = {0, 0, 0, 0}, rkl[4] = {0, 0, 0, 0}, la[4];
         bool rin[4];
@@ -776,7 +786,7 @@ __global__ void __launch_bounds__(256) k_check64_tiles(int prec, int units, int 
             rin[u] = i < n;
             la[u] = rin[u] ? (double)la2[i] : 0.0;
         }
-        for (int cs = 0; cs < CK_SUB && C0 + cs * CK_T < m; ++cs) {
+        for (int cs = 0; cs < n_sub && C0 + cs * CK_T < m; ++cs) {
             const int64_t c0 = C0 + cs * CK_T;
             double acc[4][4];
 #pragma unroll
@@ -852,7 +862,7 @@ __global__ void __launch_bounds__(256) k_check64_tiles(int prec, int units, int 
         }
     }
     __syncthreads();
-    for (int j = tid; j < CKM && C0 + j < m; j += 256) cpart[(size_t)rt * m + C0 + j] = colacc[j];
+    for (int j = tid; j < span && C0 + j < m; j += 256) cpart[(size_t)rt * m + C0 + j] = colacc[j];
 }
 
 // r64_i = sum over column tiles of the row partials (and kl), c64_j over row
@@ -878,7 +888,8 @@ __global__ void __launch_bounds__(256) k_check64_reduce(const double* rpart, con
 }
 
 size_t check64_part_doubles(int64_t n, int64_t m) {
-    return 2 * (size_t)check_tiles(m) * n + (size_t)check_tiles(n) * m;
+    const int64_t s = check_span(n, m);
+    return 2 * (size_t)((m + s - 1) / s) * n + (size_t)((n + s - 1) / s) * m;
 }
 
 hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols, int64_t n, int64_t m,
@@ -886,12 +897,13 @@ hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols,
                           hipStream_t stream) {
     const int K = pack_k(prec, d);
     const int units = pack_units(prec, d);
-    const int n_rt = check_tiles(n), n_ct = check_tiles(m);
+    const int span = check_span(n, m);
+    const int n_rt = (int)((n + span - 1) / span), n_ct = (int)((m + span - 1) / span);
     double* rpart = part;
     double* klpart = part + (size_t)n_ct * n;
     double* cpart = part + 2 * (size_t)n_ct * n;
     hipLaunchKernelGGL(k_check64_tiles, dim3((unsigned)n_ct, (unsigned)n_rt), dim3(256), 0, stream, prec, units, K,
-                       Arows, Bcols, n, m, la2, lb2, rpart, klpart, cpart);
+                       Arows, Bcols, n, m, span, la2, lb2, rpart, klpart, cpart);
     hipLaunchKernelGGL(k_check64_reduce, dim3((unsigned)((n + m + 255) / 256)), dim3(256), 0, stream, rpart, klpart,
                        cpart, n_ct, n_rt, n, m, r64, kl, c64);
     return hipGetLastError();

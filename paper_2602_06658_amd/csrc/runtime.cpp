@@ -302,8 +302,10 @@ Status Solve::configure(int64_t n, int dx, int64_t m, int dy, const gw_params& p
     if (geo_.path == 1 && E_ > 16)
         return fail(GW_EUNSUPPORTED, "source dimension below 16 needs a target dimension of at most 16");
 
-    // covariance geometry: one row group per macro tile, few column tiles;
-    // forward (source rows, payload Y) and swapped (target rows, payload X)
+    // covariance geometry: one row group per macro tile, few column tiles
+    // (about 2048 work-groups, each at least 1024 columns wide: every column
+    // tile adds a partial per row that the reduction reads back); forward
+    // (source rows, payload Y) and swapped (target rows, payload X)
     {
         const int path = geo_.path;
         auto geom = [&](int64_t rows_pad, int64_t cols_pad, int dw, int& rg, int& bc, int& mtr, int& mtc, int& tw) {
@@ -315,7 +317,7 @@ Status Solve::configure(int64_t n, int dx, int64_t m, int dy, const gw_params& p
             int want = std::max(1, (2048 + mtr - 1) / mtr);
             const size_t per_tile = (size_t)rows_pad * (tw + 2) * sizeof(float);
             const int mem_cap = (int)std::max<size_t>(1, ((size_t)1 << 30) / per_tile);
-            want = std::min(want, std::min(mem_cap, nchc));
+            want = std::min(want, std::min(mem_cap, std::max(1, nchc / 32)));
             bc = (nchc + want - 1) / want;
             mtc = (nchc + bc - 1) / bc;
         };
