@@ -115,7 +115,18 @@ def measure_peaks() -> dict | None:
     lanes = fma / (simds * clk) if clk > 0 else float("nan")
     exp_slots = fma / exp_sub - 1.0
     lanes_r = 32.0 if abs(lanes - 32.0) < 4.0 else lanes
+    overlap = None
+    if hasattr(lib, "gwp_overlap"):
+        ov = (ctypes.c_double * 4)()
+        if lib.gwp_overlap(ov) == 0:
+            m_ms, v_ms, both_ms, split_ms = (float(v) for v in ov)
+            overlap = {"mfma_ms": m_ms, "valu_ms": v_ms, "same_wave_ms": both_ms, "split_waves_ms": split_ms,
+                       "same_wave_vs_serial": both_ms / (m_ms + v_ms),
+                       "split_waves_vs_serial": split_ms / (m_ms + v_ms),
+                       "what": "BF16 pass mix per wave step (10 MFMA 32x32x16, 32 x (exp + 2 adds)), "
+                               "2 waves per SIMD; serial = MFMA alone + VALU alone"}
     return {"source": "paper_2602_06658_amd/peaks/peaks.hip", "fma_per_s": fma, "exp_sub_per_s": exp_sub,
+            "mfma_valu_overlap": overlap,
             "pass_valu_entries_per_s": entry, "mfma_bf16_tflops": bf16 / 1e12, "mfma_f32_tflops": f32 / 1e12,
             "shader_clock_ghz": clk / 1e9, "fma_lanes_per_clock_per_simd": lanes, "exp_issue_slots": exp_slots,
             # the ALU model of the stabilised pass: one exp and two adds per
@@ -912,7 +923,13 @@ def main():
                     "pass_mfma_bf16_frac": MFMA_FLOPS_PER_ENTRY["bf16"] * entries_per_launch / (avg_b * 1e-3)
                     / 1e12 / PEAK_MFMA_TFLOPS["bf16"],
                     "pass_alu_model_frac": (entries_per_launch / (avg_b * 1e-3) / peaks["alu_model_entries_per_s"]
-                                            if peaks else None)}
+                                            if peaks else None),
+                    # MFMA time (executed flops at the probe's BF16 rate) plus
+                    # VALU time (the probe's entry rate) per entry, with no
+                    # overlap of the two units
+                    "pass_serial_model_frac": (entries_per_launch / (avg_b * 1e-3) * (
+                        MFMA_FLOPS_PER_ENTRY["bf16"] / (peaks["mfma_bf16_tflops"] * 1e12)
+                        + 1.0 / peaks["pass_valu_entries_per_s"]) if peaks else None)}
         out["whole_solve_bf16"] = leg("whole bf16 solve", est, whole_bf16)
     if not args.no_serve:
         out["serving"] = leg("serving", 150, lambda: serve_bench(args, gwm, torch, dev))

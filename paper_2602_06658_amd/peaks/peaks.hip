@@ -15,6 +15,14 @@
 //   mfma_f32   v_mfma_f32_32x32x2f32   (4096 flops each)
 // and the shader clock over the fma probe (s_memtime cycles against the
 // 100 MHz s_memrealtime counter).
+//
+// gwp_overlap times whether the matrix unit and the VALU of a SIMD work at
+// the same time, on the stabilised BF16 pass's instruction mix per wave and
+// step: two dependent chains of five v_mfma_f32_32x32x16_bf16 and 32 entries
+// of one 2^x and two adds.  Four forms at two waves per SIMD (64 KiB of
+// dynamic LDS per work-group): MFMA work alone, VALU work alone, both in
+// every wave, and half the work-groups doing twice the MFMA work while the
+// other half do twice the VALU work.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -132,6 +140,49 @@ __global__ __launch_bounds__(THREADS) void k_mfma_f32(int iters, float* sink) {
     if (t == 12345.0f) sink[threadIdx.x] = t;
 }
 
+// MODE 0: MFMA only; 1: VALU only; 2: both in every wave; 3: even work-groups
+// MFMA (twice), odd ones VALU (twice)
+template <int MODE>
+__global__ __launch_bounds__(THREADS) void k_mix(int iters, float* sink) {
+    bf16x8_t a, b;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        a[k] = (__bf16)(0.001f * (float)(threadIdx.x + k));
+        b[k] = (__bf16)(0.002f * (float)(k + 1));
+    }
+    f32x16_t acc[2];
+    acc[0] = (f32x16_t)0.0f;
+    acc[1] = (f32x16_t)0.0f;
+    float rs[4] = {0.f, 0.f, 0.f, 0.f}, cs[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) cs[k] = 1.0f + 0.03f * (float)k + 1e-6f * (float)threadIdx.x;
+    const bool do_m = MODE == 0 || MODE == 2 || (MODE == 3 && !(blockIdx.x & 1));
+    const bool do_v = MODE == 1 || MODE == 2 || (MODE == 3 && (blockIdx.x & 1));
+    const int reps = MODE == 3 ? 2 : 1;
+    for (int i = 0; i < iters * reps; ++i) {
+        if (do_m) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int s = 0; s < 5; ++s) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+        }
+        if (do_v) {
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const float e = __builtin_amdgcn_exp2f(-cs[k]);
+                rs[k & 3] += e;
+                cs[k] += e;
+            }
+        }
+    }
+    float t = rs[0] + rs[1] + rs[2] + rs[3];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) t += cs[k];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += acc[0][q] + acc[1][q];
+    if (t == 12345.0f) sink[threadIdx.x] = t;
+}
+
 template <class F>
 int timed(F launch, float* ms_out) {
     hipEvent_t e0, e1;
@@ -184,6 +235,32 @@ int gwp_measure(double* out) {
     out[4] = (double)BLOCKS * (THREADS / 64) * it_mm * 4 * 4096.0 / (ms * 1e-3);
     (void)hipFree(sink);
     (void)hipFree(clk);
+    return rc ? -1 : 0;
+}
+
+// out[0..3]: milliseconds of the four k_mix forms (MFMA alone, VALU alone,
+// both in every wave, split across work-groups), 4096 work-groups of 256
+// threads, 512 steps each.  Returns 0, or -1 on a HIP error.
+int gwp_overlap(double* out) {
+    float* sink = nullptr;
+    if (hipMalloc(&sink, THREADS * sizeof(float)) != hipSuccess) return -1;
+    constexpr int MIX_BLOCKS = 4096, MIX_ITERS = 512;
+    constexpr size_t LDS = 64 * 1024;  // two work-groups (two waves per SIMD) per CU
+    int rc = 0;
+    rc |= hipFuncSetAttribute((const void*)k_mix<0>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS) == hipSuccess ? 0 : -1;
+    rc |= hipFuncSetAttribute((const void*)k_mix<1>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS) == hipSuccess ? 0 : -1;
+    rc |= hipFuncSetAttribute((const void*)k_mix<2>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS) == hipSuccess ? 0 : -1;
+    rc |= hipFuncSetAttribute((const void*)k_mix<3>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS) == hipSuccess ? 0 : -1;
+    float ms = 0.f;
+    rc |= timed([&] { k_mix<0><<<MIX_BLOCKS, THREADS, LDS>>>(MIX_ITERS, sink); }, &ms);
+    out[0] = ms;
+    rc |= timed([&] { k_mix<1><<<MIX_BLOCKS, THREADS, LDS>>>(MIX_ITERS, sink); }, &ms);
+    out[1] = ms;
+    rc |= timed([&] { k_mix<2><<<MIX_BLOCKS, THREADS, LDS>>>(MIX_ITERS, sink); }, &ms);
+    out[2] = ms;
+    rc |= timed([&] { k_mix<3><<<MIX_BLOCKS, THREADS, LDS>>>(MIX_ITERS, sink); }, &ms);
+    out[3] = ms;
+    (void)hipFree(sink);
     return rc ? -1 : 0;
 }
 
