@@ -190,6 +190,8 @@ def parse():
     ap.add_argument("--serve-landmarks", type=int, default=512)
     ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of capacity")
+    ap.add_argument("--serve-capacity-only", action="store_true",
+                    help="serving: only the capacity run (all requests submitted at once)")
     ap.add_argument("--serve-sweep", default="",
                     help="extra arrival rates (fractions of capacity, comma-separated) replayed through the "
                          "batching server, e.g. 0.5,0.9,1.1")
@@ -250,6 +252,9 @@ def serve_bench(args, gwm, torch, dev) -> dict:
         return res
 
     cap = run(args.serve_slots, None)
+    if args.serve_capacity_only:
+        return {"capacity_solves_per_s": cap["solves_per_s"], "capacity_entries_per_s": cap["entries_per_s"],
+                "wall_s": cap["wall_s"], "slots": args.serve_slots}
     rate = args.serve_load * cap["solves_per_s"]
     gaps = arrivals / rate  # the trace is a unit-rate Poisson process
     batched = run(args.serve_slots, gaps)

@@ -1,11 +1,12 @@
 // Serving loop: continuous batching of independent CNT-GW solves (Algorithm 1)
 // on one GPU.
 //
-// Two host threads share the work of the requests a server has admitted:
+// Host threads share the work of the requests a server has admitted:
 //
-// * the setup thread takes admitted requests in FIFO order and runs their
-//   setup (validation, lifting with its landmark eigensolve, initial state) on
-//   a stream of its own, then records an event and hands the request over;
+// * setup workers (SETUP_WORKERS of them) take admitted requests in FIFO
+//   order and each runs a request's setup (validation, lifting with its
+//   landmark eigensolve, initial state) on a stream and rocBLAS handle of its
+//   own, then records an event and hands the request over;
 // * the round thread issues rounds on the context's stream: every active
 //   request advances by one Sinkhorn iteration.  Symmetric MFMA-path requests
 //   go through one batched launch per kernel (pass, safe pass, combine, retry
@@ -15,7 +16,7 @@
 //   request's FP64 check (Appendix A.1's Err) and result readback are queued
 //   behind its last round and collected when an event says they are done.
 //
-// Neither thread waits for the other's GPU work: a request joins the rounds
+// No thread waits for another's GPU work: a request joins the rounds
 // once the round stream has been made to wait on its setup event, so setups
 // and their host-side synchronisations overlap the rounds of others.
 // Requests are admitted while a slot is free and their planned device
@@ -76,18 +77,24 @@ struct Request {
 
 }  // namespace
 
+// Setup workers: each runs whole request setups (validation, lifting with
+// its landmark eigensolve, initial state) on a stream and a rocBLAS handle of
+// its own.  The landmark eigensolve is a long chain of small launches, so
+// several setups in flight keep the rounds fed with new requests.
+constexpr int SETUP_WORKERS = 3;
+
 struct gw_server {
     gwr::Ctx* base = nullptr;
     int max_slots = 1;
     size_t budget = 0;
-    hipStream_t setup_stream = nullptr;
-    std::thread th, worker;
+    hipStream_t setup_stream[SETUP_WORKERS] = {};
+    std::thread th, worker[SETUP_WORKERS];
     std::mutex mu;
     std::condition_variable cv_work, cv_setup, cv_done;
     bool stop = false;
     uint64_t next_ticket = 1;
     std::deque<uint64_t> queue;           // submitted, not admitted
-    std::deque<Request*> to_setup;        // admitted, waiting for the setup thread
+    std::deque<Request*> to_setup;        // admitted, waiting for a setup worker
     std::vector<Request*> ready;          // set up, waiting to join the rounds
     std::vector<std::unique_ptr<Slot>> free_slots;
     std::vector<std::unique_ptr<Slot>> used_slots;
@@ -95,7 +102,7 @@ struct gw_server {
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     gw_server_stats stats{};
     size_t resident = 0;                  // planned footprints of admitted requests
-    void* rocblas = nullptr;              // used by the setup thread only
+    void* rocblas[SETUP_WORKERS] = {};    // one per setup worker
     // round thread only
     std::vector<Request*> active, finishing;
 };
@@ -182,7 +189,8 @@ void release_slot(gw_server* s, Request* q) {
     Slot* sl = q->slot;
     q->slot = nullptr;
     if (!sl) return;
-    if (sl->ctx->rocblas == s->rocblas) sl->ctx->rocblas = nullptr;  // shared handle stays
+    for (void* h : s->rocblas)
+        if (sl->ctx->rocblas == h) sl->ctx->rocblas = nullptr;  // the worker's handle stays
     const size_t before = slot_bytes(*sl);
     gwr::release_landmarks(*sl->ctx);
     if (s->budget) sl->ctx->ws.release_all();
@@ -211,9 +219,9 @@ void complete(gw_server* s, Request* q, ReqState st, gw_status code, const std::
     s->cv_work.notify_all();
 }
 
-// Setup of one request on the setup stream (validation, lifting, initial
-// state); the host-side waits in it block only the setup thread.
-gwr::Status start(gw_server* s, Request* q) {
+// Setup of one request on setup worker w's stream (validation, lifting,
+// initial state); the host-side waits in it block only that worker.
+gwr::Status start(gw_server* s, Request* q, int w) {
     q->slot = acquire_slot(s);
     gwr::Ctx& c = *q->slot->ctx;
     const size_t before = slot_bytes(*q->slot);
@@ -227,16 +235,16 @@ gwr::Status start(gw_server* s, Request* q) {
             account(s, (int64_t)after - (int64_t)before);
         }
     } acct{s, q->slot, before};
-    c.stream = s->setup_stream;
+    c.stream = s->setup_stream[w];
     configure_sides(c, q->r);
     if (q->r.penalty == GW_PEN_POWER) {
-        if (!s->rocblas) {
+        if (!s->rocblas[w]) {
             rocblas_handle h;
             if (rocblas_create_handle(&h) != rocblas_status_success)
                 return gwr::fail(GW_EDEVICE, "rocblas_create_handle");
-            s->rocblas = h;
+            s->rocblas[w] = h;
         }
-        c.rocblas = s->rocblas;
+        c.rocblas = s->rocblas[w];
     }
     q->solve = std::make_unique<gwr::Solve>(c, "q.");
     const gw_request& r = q->r;
@@ -250,7 +258,7 @@ gwr::Status start(gw_server* s, Request* q) {
     return gwr::Status::ok();
 }
 
-void setup_main(gw_server* s) {
+void setup_main(gw_server* s, int w) {
     (void)hipSetDevice(s->base->device);
     for (;;) {
         Request* q = nullptr;
@@ -265,9 +273,9 @@ void setup_main(gw_server* s) {
             complete(s, q, RQ_CANCELLED, GW_ECANCELLED, "cancelled");
             continue;
         }
-        gwr::Status st = start(s, q);
+        gwr::Status st = start(s, q, w);
         if (!st.good()) {
-            (void)hipStreamSynchronize(s->setup_stream);
+            (void)hipStreamSynchronize(s->setup_stream[w]);
             release_slot(s, q);
             complete(s, q, RQ_FAILED, st.code, st.msg);
             continue;
@@ -461,7 +469,8 @@ void cancel_unstarted(gw_server* s, Request* q) {
 }
 
 void destroy_slot(gw_server* s, Slot& sl) {
-    if (sl.ctx->rocblas == s->rocblas) sl.ctx->rocblas = nullptr;
+    for (void* h : s->rocblas)
+        if (sl.ctx->rocblas == h) sl.ctx->rocblas = nullptr;
     gwr::release_landmarks(*sl.ctx);
     (void)hipEventDestroy(sl.ev);
 }
@@ -479,11 +488,13 @@ gw_status gw_server_create(gw_ctx* ctx, int max_slots, size_t hbm_budget_bytes, 
     s->base = &ctx->c;
     s->max_slots = max_slots;
     s->budget = hbm_budget_bytes;
-    if (hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete s;
-        return GW_EDEVICE;
-    }
-    s->worker = std::thread(setup_main, s);
+    for (int w = 0; w < SETUP_WORKERS; ++w)
+        if (hipStreamCreateWithFlags(&s->setup_stream[w], hipStreamNonBlocking) != hipSuccess) {
+            for (int k = 0; k < w; ++k) (void)hipStreamDestroy(s->setup_stream[k]);
+            delete s;
+            return GW_EDEVICE;
+        }
+    for (int w = 0; w < SETUP_WORKERS; ++w) s->worker[w] = std::thread(setup_main, s, w);
     s->th = std::thread(round_main, s);
     *out = s;
     return GW_OK;
@@ -551,7 +562,7 @@ gw_status gw_server_cancel(gw_server* s, uint64_t ticket) {
         s->stats.queued = (int32_t)s->queue.size();
         s->cv_done.notify_all();
     } else if (q->state == RQ_SETUP || q->state == RQ_ACTIVE) {
-        q->cancel = true;  // taken by the setup thread or the next round
+        q->cancel = true;  // taken by a setup worker or the next round
     }
     return GW_OK;
 }
@@ -571,9 +582,10 @@ void gw_server_destroy(gw_server* s) {
         s->cv_work.notify_all();
         s->cv_setup.notify_all();
     }
-    if (s->worker.joinable()) s->worker.join();
+    for (auto& t : s->worker)
+        if (t.joinable()) t.join();
     if (s->th.joinable()) s->th.join();
-    (void)hipStreamSynchronize(s->setup_stream);
+    for (hipStream_t st : s->setup_stream) (void)hipStreamSynchronize(st);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (Request* q : s->to_setup) cancel_unstarted(s, q);
@@ -592,8 +604,9 @@ void gw_server_destroy(gw_server* s) {
     for (auto& sl : s->used_slots) destroy_slot(s, *sl);
     s->free_slots.clear();
     s->used_slots.clear();
-    if (s->rocblas) rocblas_destroy_handle((rocblas_handle)s->rocblas);
-    (void)hipStreamDestroy(s->setup_stream);
+    for (void* h : s->rocblas)
+        if (h) rocblas_destroy_handle((rocblas_handle)h);
+    for (hipStream_t st : s->setup_stream) (void)hipStreamDestroy(st);
     delete s;
 }
 
