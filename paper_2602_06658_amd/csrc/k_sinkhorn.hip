@@ -372,18 +372,10 @@ __global__ void __launch_bounds__(THREADS) k_pass_safe(PassArgs p) {
     pass_safe_body<C, RW>(p, blockIdx.x);
 }
 
-// The batched safe pass runs in every serving round, and in most rounds no
-// request is in the safe mode: its grid is capped (SAFE_BATCH_GRID) and each
-// work-group walks the macro tiles, so such a launch costs a few hundred
-// flag reads rather than one work-group per tile.
-constexpr int SAFE_BATCH_GRID = 512;
 template <class C, int RW>
 __global__ void __launch_bounds__(THREADS) k_pass_safe_batch(PassBatch b) {
-    for (int wg = blockIdx.x; wg < b.start[b.n]; wg += gridDim.x) {
-        const int r = batch_slot(b.start, b.n, wg);
-        __syncthreads();  // the previous tile's LDS reads are done
-        pass_safe_body<C, RW>(b.req[r], wg - b.start[r]);
-    }
+    const int r = batch_slot(b.start, b.n, blockIdx.x);
+    pass_safe_body<C, RW>(b.req[r], blockIdx.x - b.start[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,9 +643,7 @@ static size_t pass_lds_bytes(const Geometry& g, int safe) {
 template <class C, int RW>
 static hipError_t launch_mfma_batch(const PassBatch& b, size_t lds, int safe, hipStream_t stream) {
     if (safe)
-        hipLaunchKernelGGL((k_pass_safe_batch<C, RW>),
-                           dim3(b.start[b.n] < SAFE_BATCH_GRID ? b.start[b.n] : SAFE_BATCH_GRID), dim3(THREADS), lds,
-                           stream, b);
+        hipLaunchKernelGGL((k_pass_safe_batch<C, RW>), dim3(b.start[b.n]), dim3(THREADS), lds, stream, b);
     else
         hipLaunchKernelGGL((k_pass_stab_batch<C, RW>), dim3(b.start[b.n]), dim3(THREADS), lds, stream, b);
     return hipGetLastError();
