@@ -219,34 +219,58 @@ hipError_t launch_pack_pot(const float* ph, const float* pl, int64_t rows_pad, i
 // first != 0: start from f0/g0 (NULL = 0) instead of the previous state.
 // ---------------------------------------------------------------------------
 
-__global__ void k_prologue_cols(const float* Y, int64_t m, int64_t m_pad, int dE, int dD, const float* gamma,
-                                const float* ynorm, const float* lb2, const float* g0, int first, int expanded,
-                                double kappa, double kappa_old, float* Zout, double* beta, float* Vh, float* Vl,
-                                float* ms) {
+// One work-group takes 256 / dD columns; thread (column, c) computes
+// (Gamma Y_j)_c with the products added in e order, and one thread per column
+// adds |Z_j|^2 in c order and rebases V_j, so every value is the one a
+// thread-per-column loop gives.  Gamma sits in LDS with rows padded by one
+// float (no bank conflicts between the c threads).
+constexpr int PRO_THREADS = 256;
+__global__ void __launch_bounds__(PRO_THREADS) k_prologue_cols(const float* Y, int64_t m, int64_t m_pad, int dE,
+                                                               int dD, const float* gamma, const float* ynorm,
+                                                               const float* lb2, const float* g0, int first,
+                                                               int expanded, double kappa, double kappa_old,
+                                                               float* Zout, double* beta, float* Vh, float* Vl,
+                                                               float* ms) {
     extern __shared__ float gsh_dyn[];
-    const bool in_lds = dD * dE <= 16384;
+    __shared__ float sbuf[PRO_THREADS];
+    const int gs = dE + 1;  // padded row stride of Gamma in LDS
+    const bool in_lds = dD * gs <= 16128;  // with sbuf, at most 64 KiB of LDS
     if (in_lds) {
-        for (int t = threadIdx.x; t < dD * dE; t += blockDim.x) gsh_dyn[t] = gamma[t];
+        for (int t = threadIdx.x; t < dD * dE; t += blockDim.x) gsh_dyn[(t / dE) * gs + t % dE] = gamma[t];
         __syncthreads();
     }
-    const float* gsh = in_lds ? gsh_dyn : gamma;
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= m_pad) return;
+    const int cpb = PRO_THREADS / dD;  // columns per work-group (dD <= 256)
+    const int jl = threadIdx.x / dD, c = threadIdx.x - jl * dD;
+    const int64_t j = blockIdx.x * (int64_t)cpb + jl;
+    const bool act = jl < cpb && j < m_pad;
+    const float sc = expanded ? (float)(2.0 * kappa) : 1.f;
+    if (act) {
+        if (j < m) {
+            float s = 0.f;
+            if (in_lds) {
+                for (int e = 0; e < dE; ++e) s = fmaf(gsh_dyn[c * gs + e], Y[j * dE + e], s);
+            } else {
+                for (int e = 0; e < dE; ++e) s = fmaf(gamma[c * dE + e], Y[j * dE + e], s);
+            }
+            Zout[j * dD + c] = sc * s;
+            sbuf[jl * dD + c] = s;
+        } else {
+            Zout[j * dD + c] = 0.f;
+        }
+    }
+    __syncthreads();
+    if (!act || c != 0) return;
     if (j >= m) {
-        for (int c = 0; c < dD; ++c) Zout[j * dD + c] = 0.f;
         Vh[j] = -INFINITY;
         Vl[j] = 0.f;
         ms[j] = 0.f;
         if (expanded) beta[j] = 0.0;
         return;
     }
-    const float sc = expanded ? (float)(2.0 * kappa) : 1.f;
     double z2 = 0.0;
-    for (int c = 0; c < dD; ++c) {
-        float s = 0.f;
-        for (int e = 0; e < dE; ++e) s = fmaf(gsh[c * dE + e], Y[j * dE + e], s);
-        Zout[j * dD + c] = sc * s;
-        z2 += (double)s * (double)s;
+    for (int k = 0; k < dD; ++k) {
+        const double v = (double)sbuf[jl * dD + k];
+        z2 += v * v;
     }
     const double mj = (double)ynorm[j];
     const double lb = (double)lb2[j];
@@ -275,9 +299,12 @@ hipError_t launch_prologue_cols(const float* Y, int64_t m, int64_t m_pad, int dE
                                 const float* ynorm, const float* lb2, const float* g0, int first, int expanded,
                                 double kappa, double kappa_old, float* Zout, double* beta, float* Vh, float* Vl,
                                 float* ms, hipStream_t stream) {
-    const size_t sh = dD * dE <= 16384 ? (size_t)dD * dE * sizeof(float) : 0;
-    hipLaunchKernelGGL(k_prologue_cols, dim3((unsigned)((m_pad + 127) / 128)), dim3(128), sh, stream, Y, m, m_pad, dE,
-                       dD, gamma, ynorm, lb2, g0, first, expanded, kappa, kappa_old, Zout, beta, Vh, Vl, ms);
+    if (dD < 1 || dD > PRO_THREADS) return hipErrorInvalidValue;
+    const size_t sh = dD * (dE + 1) <= 16128 ? (size_t)dD * (dE + 1) * sizeof(float) : 0;
+    const int cpb = PRO_THREADS / dD;
+    hipLaunchKernelGGL(k_prologue_cols, dim3((unsigned)((m_pad + cpb - 1) / cpb)), dim3(PRO_THREADS), sh, stream, Y,
+                       m, m_pad, dE, dD, gamma, ynorm, lb2, g0, first, expanded, kappa, kappa_old, Zout, beta, Vh, Vl,
+                       ms);
     return hipGetLastError();
 }
 
