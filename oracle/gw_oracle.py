@@ -871,6 +871,33 @@ def coarsen(X, a, init_idx, n_lloyd: int):
     return C32[kept].copy(), ac, assign, kept
 
 
+def kmeans_plain(X, a, init_idx, n_lloyd: int):
+    """Weighted K-Means as the textbook states it (Coarsen, Appendix B,
+    Multiscale-GW), in float64 throughout: n_lloyd Lloyd iterations from the
+    rows init_idx, each assigning every row to its nearest centroid (ties to
+    the lowest index) and moving each centroid to the a-weighted mean of its
+    cluster (an empty cluster keeps its centroid).  No rounding is imposed:
+    coarsen is this algorithm with its sums on a fixed-point grid and its
+    distances in single precision, and the two agree wherever no assignment
+    is decided within single-precision rounding of a tie.
+    Returns (centroids k x D, cluster weights k, assignment n)."""
+    X = np.asarray(X, np.float64)
+    a = np.asarray(a, np.float64)
+    C = X[np.asarray(init_idx, dtype=np.int64)].copy()
+    k = C.shape[0]
+    assign = np.zeros(X.shape[0], dtype=np.int64)
+    w = np.zeros(k)
+    for _ in range(n_lloyd):
+        d2 = np.sum((X[:, None, :] - C[None, :, :]) ** 2, axis=2)
+        assign = np.argmin(d2, axis=1)
+        w = np.bincount(assign, weights=a, minlength=k)
+        sums = np.zeros_like(C)
+        np.add.at(sums, assign, a[:, None] * X)
+        nz = w > 0
+        C[nz] = sums[nz] / w[nz][:, None]
+    return C, w, assign
+
+
 def target_lift(Y, gamma) -> np.ndarray:
     """Zbar_j = [Gamma Y_j, |Y_j|^2 / 2] (Algorithm 1, lifted target)."""
     Y = np.asarray(Y, np.float64)

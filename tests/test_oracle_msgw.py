@@ -1,7 +1,8 @@
 """Pins of the multiscale oracle (Appendix B, Multiscale-GW: Coarsen,
 Algorithm 8 Interpolate, Algorithm 7) against facts that do not come from
 the oracle itself: a Lloyd iteration worked by hand, scikit-learn's K-Means
-on the same start, exact identities (one point per cluster, conservation of
+on the same start, the textbook float64 Lloyd iteration (kmeans_plain) of
+which coarsen is the fixed-point form, exact identities (one point per cluster, conservation of
 weight and mean), the paper's own bilinear form of Algorithm 8 evaluated
 with scipy's logsumexp, the Sinkhorn fixed point, and the fixed point of
 Algorithm 1 carried from the coarse to the fine scale."""
@@ -206,3 +207,22 @@ def test_msgw_invariant_under_rotation_of_one_side():
     l1 = O.egw_objective(O.centre(X, a), O.centre(Y, b), a, b, r1.fine.pi, 0.1)
     l2 = O.egw_objective(O.centre(X, a), O.centre(Y @ R.T, b), a, b, r2.fine.pi, 0.1)
     assert abs(l1 - l2) <= 1e-5 * abs(l1)
+
+
+def test_coarsen_is_plain_kmeans_away_from_ties():
+    # coarsen fixes the precision of the sums (a 2^-S grid) and of the
+    # distances (single precision); on generic inputs, where no assignment
+    # falls within that rounding of a tie, it is the float64 textbook
+    # algorithm: the same assignments and kept clusters, the cluster weights
+    # and centroids to single precision
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        X = _gmm(rng, 400, 3, k=6, sigma=0.08).astype(np.float32)
+        a = rng.dirichlet(np.ones(400) * 2).astype(np.float32)
+        init = rng.choice(400, size=12, replace=False)
+        Xc, ac, assign, kept = O.coarsen(X, a, init, 5)
+        C, w, assign_p = O.kmeans_plain(X, a, init, 5)
+        assert np.array_equal(assign, assign_p), trial
+        assert np.array_equal(kept, np.nonzero(w > 0)[0])
+        assert np.allclose(ac, w[kept], rtol=1e-6, atol=0)
+        assert np.abs(Xc - C[kept]).max() <= 4e-7 * np.abs(C).max()
