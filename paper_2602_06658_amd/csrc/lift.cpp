@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <iterator>
 #include <numeric>
 
 #include "gw_lift.h"
@@ -107,6 +108,101 @@ static Status fit_landmarks(Ctx& c, int side, const float* x, int64_t n, int d, 
     lm.d_in = d;
     lm.dim = D;
     lm.fitted = true;
+    return Status::ok();
+}
+
+// Both sides' landmark maps with one batched eigensolve.  A 512 x 512 dsyevd
+// is a chain of some 2,800 small launches, and the batched routine issues
+// the same chain for both matrices.  Fits only when both sides use the power
+// penalty, neither is fitted and both have the same landmark count and
+// valid settings; otherwise it leaves the sides to the per-side fit (which
+// also reports any error).  The per-matrix arithmetic is that of the
+// single-matrix routine.
+Status fit_landmarks_pair(Ctx& c, const float* x, int64_t n, int dx, const float* y, int64_t m, int dy,
+                          const std::string& tag) {
+    SideCfg* sc[2] = {&c.side[0], &c.side[1]};
+    const float* pts_in[2] = {x, y};
+    const int64_t cnt[2] = {n, m};
+    const int din[2] = {dx, dy};
+    std::vector<int64_t> idx[2];
+    for (int k = 0; k < 2; ++k) {
+        const SideCfg& s = *sc[k];
+        if (s.kind != GW_PEN_POWER || s.lm.fitted) return Status::ok();
+        idx[k] = s.explicit_idx.empty() ? seeded_landmarks(cnt[k], s.n_landmarks, s.seed) : s.explicit_idx;
+        for (int64_t v : idx[k])
+            if (v < 0 || v >= cnt[k]) return Status::ok();
+        if ((int)idx[k].size() < s.lifted_dim + 1 || din[k] > 32) return Status::ok();
+    }
+    if (idx[0].size() != idx[1].size()) return Status::ok();
+    const int nl = (int)idx[0].size();
+    Status st;
+    auto& ws = c.ws;
+    double* K = ws.get_t<double>(tag + "pairK", 2 * (size_t)nl * nl, &st);
+    double* eval = ws.get_t<double>(tag + "pairev", 2 * (size_t)nl, &st);
+    double* ework = ws.get_t<double>(tag + "pairew", 2 * (size_t)nl, &st);
+    int* info = ws.get_t<int>(tag + "pairinfo", 2, &st);
+    int64_t* didx[2];
+    double* rmean[2];
+    double* g[2];
+    for (int k = 0; k < 2; ++k) {
+        const std::string t = tag + "pair" + std::to_string(k);
+        didx[k] = (int64_t*)ws.get(t + "idx", nl * sizeof(int64_t), &st);
+        rmean[k] = ws.get_t<double>(t + "r", nl, &st);
+        g[k] = ws.get_t<double>(t + "g", 1, &st);
+    }
+    if (!st.good()) return st;
+    for (int k = 0; k < 2; ++k) {
+        Landmarks& lm = sc[k]->lm;
+        free_lm(lm);
+        const int D = sc[k]->lifted_dim, d = din[k];
+        GW_HIP(hipMalloc(&lm.pts, (size_t)nl * d * sizeof(float)));
+        GW_HIP(hipMalloc(&lm.W, (size_t)nl * D * sizeof(float)));
+        GW_HIP(hipMalloc(&lm.chat, (size_t)nl * sizeof(float)));
+        GW_HIP(hipMalloc(&lm.sumW, (size_t)D * sizeof(float)));
+        GW_HIP(hipMemcpyAsync(didx[k], idx[k].data(), nl * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+        GW_HIP(gwk::launch_gather(pts_in[k], d, didx[k], nl, lm.pts, c.stream));
+        GW_HIP(gwk::launch_landmark_kernel(lm.pts, nl, d, sc[k]->p, K + (size_t)k * nl * nl, rmean[k], g[k],
+                                           c.stream));
+    }
+    if (!c.rocblas) {
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return fail(GW_EDEVICE, "rocblas_create_handle");
+        c.rocblas = h;
+    }
+    rocblas_handle h = (rocblas_handle)c.rocblas;
+    if (rocblas_set_stream(h, c.stream) != rocblas_status_success) return fail(GW_EDEVICE, "rocblas_set_stream");
+    if (rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, nl, K, nl,
+                                         (rocblas_stride)nl * nl, eval, nl, ework, nl, info, 2) != rocblas_status_success)
+        return fail(GW_EDEVICE, "rocsolver_dsyevd_strided_batched");
+    for (int k = 0; k < 2; ++k) {
+        Landmarks& lm = sc[k]->lm;
+        GW_HIP(gwk::launch_nystrom_weights(K + (size_t)k * nl * nl, eval + (size_t)k * nl, nl, sc[k]->lifted_dim,
+                                           1e-12, rmean[k], lm.W, lm.chat, lm.sumW, c.stream));
+    }
+    int hinfo[2] = {0, 0};
+    double hg[2] = {0.0, 0.0};
+    std::vector<double> hev(2 * (size_t)nl);
+    GW_HIP(hipMemcpyAsync(hinfo, info, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    for (int k = 0; k < 2; ++k) GW_HIP(hipMemcpyAsync(&hg[k], g[k], sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    GW_HIP(hipMemcpyAsync(hev.data(), eval, 2 * (size_t)nl * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    GW_HIP(hipStreamSynchronize(c.stream));
+    for (int k = 0; k < 2; ++k) {
+        Landmarks& lm = sc[k]->lm;
+        if (hinfo[k] != 0) {
+            free_lm(sc[0]->lm);
+            free_lm(sc[1]->lm);
+            return fail(GW_ENUMERIC, "landmark eigensolve did not converge");
+        }
+        const int D = sc[k]->lifted_dim;
+        const double* ev = hev.data() + (size_t)k * nl;
+        lm.cbarbar = hg[k];
+        lm.lambda.assign(std::reverse_iterator<const double*>(ev + nl),
+                         std::reverse_iterator<const double*>(ev + nl) + std::min(D, nl));
+        lm.n_l = nl;
+        lm.d_in = din[k];
+        lm.dim = D;
+        lm.fitted = true;
+    }
     return Status::ok();
 }
 

@@ -370,6 +370,7 @@ Status Solve::setup(const float* x, int64_t n, int dx, const float* a, const flo
 
     // lifting
     c_.prof.begin(GW_PROF_LIFT, st_);
+    GW_TRY(fit_landmarks_pair(c_, x, n, dx, y, m, dy, tag_));
     GW_TRY(lift_side(c_, 0, x, n, dx, a, X_, n_pad_, tag_));
     GW_TRY(lift_side(c_, 1, y, m, dy, b, Y_, m_pad_, tag_));
     c_.prof.end(st_);

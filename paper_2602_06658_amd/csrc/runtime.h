@@ -312,6 +312,10 @@ void release_landmarks(Ctx& c);
 void free_landmarks(Landmarks& lm);
 Status lift_nystrom(Ctx& c, int side, const float* x, int64_t n, int d, const float* w, float* X, int64_t n_pad,
                     const std::string& tag);
+// Fit both sides' landmark maps with one batched eigensolve when both use the
+// power penalty unfitted with equal landmark counts; otherwise does nothing.
+Status fit_landmarks_pair(Ctx& c, const float* x, int64_t n, int dx, const float* y, int64_t m, int dy,
+                          const std::string& tag);
 }  // namespace gwr
 
 namespace gwr {
