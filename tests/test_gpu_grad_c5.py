@@ -9,9 +9,12 @@ ends far from a feasible coupling (marginal error ~3e-2, still ~2e-2 after
 plus a polish reaches a marginal error below 1e-6.  Even there the outer
 iteration still drifts slowly at this size, and central differences along
 random directions (projections ~30x below the gradient's) pick that drift up
-(errors of 5-30% in measurements); they are not checked here.  The
-oracle's converged gradient is compared row by row on a subsample of this
-workload in test_gpu_grad.py.
+(errors of 5-30% in measurements); at this size they are not checked.  The
+second test checks 32 random weight directions and the position gradient at
+h = 1e-3 on a 400 x 300 draw of the same workload, polished to the FP32
+floor of the marginal error (about 1e-6).  The oracle's
+converged gradient is compared row by row on a subsample of this workload
+in test_gpu_grad.py.
 
 Checked: central differences (h = 1e-3) of the polished EGW objective, each
 solve warm-started from the polished state, along the position gradient and
@@ -68,3 +71,55 @@ def test_c5_gradients_against_finite_differences(gw):
     print(f"  weights:   fd {fd_a:.6e} analytic {an_a:.6e} rel {rel_a:.2e}")
     assert pol["marginal_err"] < 1e-4
     assert rel_x < 5e-2 and rel_a < 5e-2
+
+
+def test_random_direction_differences_on_a_small_draw(gw):
+    # The differentiation workload's structure (d = 16 mixture, Dirichlet(1)
+    # weights, |x - x'| lifted to D = 64) at 400 x 300 points, polished to the
+    # FP32 floor of the marginal error (about 1e-6): central differences at
+    # h = 1e-3 along 32 random simplex-tangent directions of the weights and
+    # along the position gradient, against the envelope gradient.  |x - x'|
+    # has a kink at zero distance and the landmarks are points of the
+    # measure, which sit on their own kink: the position direction moves the
+    # other points only.  Random position directions are not checked: their
+    # projections (about 5e-4 here) are below what the FP32 objective
+    # resolves at this h (re-solves of one state differ by up to 2e-6).
+    prob = config5_grad(n=400, m=300)
+    a64 = prob.a / prob.a.sum()
+    x, a, y, b = dev(prob.x), dev(a64), dev(prob.y), dev(prob.b / prob.b.sum())
+    ctx = gw.Context()
+    lmx = landmark_indices(prob.n, 128, 5201)
+    for side, (n, seed) in enumerate(((prob.n, 5201), (prob.m, 5202))):
+        ctx.set_penalty(side, "power", p=1.0, lifted_dim=64, n_landmarks=128)
+        ctx.set_landmarks(side, landmark_indices(n, 128, seed))
+    base = ctx.solve(x, a, y, b, EPS, EPS, 20, 200)
+    pol = ctx.loss_and_grad(x, a, y, b, EPS, EPS, 10, 1000, gamma0=base["gamma"], f0=base["f"], g0=base["g"])
+    print(f"small draw: polished Err {pol['marginal_err']:.2e}, loss {pol['egw_objective']:.8g}", flush=True)
+    assert pol["marginal_err"] < 1e-5
+    state = dict(gamma0=pol["gamma"], f0=pol["f"], g0=pol["g"])
+
+    def objective(xx, aa):
+        return ctx.solve(xx, aa, y, b, EPS, EPS, 6, 300, **state)["egw_objective"]
+
+    gx = pol["grad_x"].cpu().numpy().astype(np.float64)
+    ga = pol["grad_a"].cpu().numpy().astype(np.float64)
+    free = np.ones(prob.n, bool)
+    free[np.asarray(lmx)] = False
+    d = gx * free[:, None]
+    d /= np.linalg.norm(d)
+    fd_g = (objective(x + H * dev(d), a) - objective(x - H * dev(d), a)) / (2 * H)
+    an_g = float((gx * d).sum())
+    rng = np.random.default_rng(77)
+    fd_a, an_a = [], []
+    for _ in range(32):
+        r = rng.standard_normal(a64.shape)
+        da = a64 * (r - a64 @ r)
+        da /= np.abs(da / a64).max()                      # relative change of each weight <= 1
+        fd_a.append((objective(x, a + H * dev(da)) - objective(x, a - H * dev(da))) / (2 * H))
+        an_a.append(float(ga @ da))
+    fd_a, an_a = np.array(fd_a), np.array(an_a)
+    ea = np.linalg.norm(fd_a - an_a) / np.linalg.norm(an_a)
+    eg = abs(fd_g - an_g) / abs(an_g)
+    print(f"  position gradient direction: fd {fd_g:.6e} analytic {an_g:.6e} rel {eg:.2e}; "
+          f"32 random weight directions: |fd - analytic| / |analytic| = {ea:.2e}", flush=True)
+    assert eg < 3e-2 and ea < 1e-1
