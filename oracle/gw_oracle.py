@@ -678,6 +678,54 @@ def sgw_grad_positions(a, b, x, y, eps, tol=1e-13):
     return gx - 0.5 * (sx + tx), gy - 0.5 * (sy + ty)
 
 
+def sgw_grad_weights(a, b, x, y, eps, tol=1e-13):
+    """Weight gradient of the Sinkhorn-GW divergence (Section 4, "Entropic
+    Bias") for the squared Euclidean penalty.  GW_eps(alpha, beta) depends on
+    a through its source marginal and on b through its target marginal; by
+    the Lagrangian of the EGW problem (as in grad_weights) each derivative
+    along the simplex is the EOT potential of the linearised cost
+    2 sum_kl (cX - cY)^2 pi*_kl on that side.  GW_eps(alpha, alpha) has a in
+    both marginals, so its derivative is the sum of its two potentials.
+    Solves converged at eps (tol and tol / 10); returns (grad_a, grad_b),
+    each centred (sum a_i grad_a_i = 0), since constants do not matter on
+    the simplex."""
+    def pots(p, P, q, Q):
+        PP, QQ = centre(P, p), centre(Q, q)
+        gam, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps, tol=tol, sink_tol=tol / 10)
+        c = full_linearisation(sqdist(PP, PP), sqdist(QQ, QQ), pi)
+        return sinkhorn_converged(p, q, c, eps, tol=tol, max_iter=200000)
+
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    fxy, gxy = pots(a, x, b, y)
+    fxx, gxx = pots(a, x, a, x)
+    fyy, gyy = pots(b, y, b, y)
+    ga = fxy - 0.5 * (fxx + gxx)
+    gb = gxy - 0.5 * (fyy + gyy)
+    return ga - a @ ga, gb - b @ gb
+
+
+def sgw_grad_weights_lifted(a, b, x, y, eps, lmx: Landmarks, lmy: Landmarks, tol=1e-13):
+    """sgw_grad_weights for a penalty lifted by frozen landmark maps (as in
+    sgw_grad_positions_lifted): each problem's cost matrices are the squared
+    distances of the embedded, re-centred features.  Returns (grad_a,
+    grad_b), centred."""
+    def pots(p, P, lmP, q, Q, lmQ):
+        PP, QQ = landmark_features(P, p, lmP), landmark_features(Q, q, lmQ)
+        gam, pi, _, _ = cnt_gw_converged(p, q, PP, QQ, eps, tol=tol, sink_tol=tol / 10)
+        c = full_linearisation(sqdist(PP, PP), sqdist(QQ, QQ), pi)
+        return sinkhorn_converged(p, q, c, eps, tol=tol, max_iter=200000)
+
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    fxy, gxy = pots(a, x, lmx, b, y, lmy)
+    fxx, gxx = pots(a, x, lmx, a, x, lmx)
+    fyy, gyy = pots(b, y, lmy, b, y, lmy)
+    ga = fxy - 0.5 * (fxx + gxx)
+    gb = gxy - 0.5 * (fyy + gyy)
+    return ga - a @ ga, gb - b @ gb
+
+
 def sgw_grad_positions_lifted(a, b, x, y, eps, lmx: Landmarks, lmy: Landmarks, tol=1e-13):
     """Position gradient of the Sinkhorn-GW divergence for a penalty lifted
     by frozen landmark maps (|x - x'|^p through kernel PCA, Section 5,

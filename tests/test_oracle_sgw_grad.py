@@ -6,7 +6,9 @@ where each EGW problem has one attractor:
   solves, along random directions for x and for y;
 * zero at isometric measures: SGW >= 0 with equality there (Theorem 4.3),
   so such a pair is a minimum and the gradient vanishes, although each of
-  the three envelope gradients is far from zero."""
+  the three envelope gradients is far from zero.
+The same two pins hold the weight gradients (sgw_grad_weights), along
+directions tangent to the simplex, and the lifted penalty's versions."""
 import numpy as np
 
 from oracle import gw_oracle as O
@@ -120,3 +122,69 @@ def test_lifted_gradient_vanishes_between_isometric_measures():
     scale = np.abs(pair).max()
     assert scale > 1e-2
     assert np.abs(gx).max() < 1e-7 * scale and np.abs(gy).max() < 1e-7 * scale
+
+
+# Weight gradients (sgw_grad_weights): each EGW problem's derivative along the
+# simplex is the EOT potential of its linearised cost on that side, and
+# GW_eps(alpha, alpha) carries a in both marginals
+
+
+def _tangent(rng, w):
+    u = rng.standard_normal(len(w))
+    d = w * (u - w @ u)
+    return d / np.linalg.norm(d)
+
+
+def test_weight_gradient_matches_finite_differences():
+    rng = np.random.default_rng(42)
+    x, a = _measure(rng, 9, 2)
+    y, b = _measure(rng, 8, 2)
+    ga, gb = O.sgw_grad_weights(a, b, x, y, EPS)
+    assert abs(a @ ga) < 1e-12 * np.abs(ga).max() and abs(b @ gb) < 1e-12 * np.abs(gb).max()
+    h = 1e-5
+    for _ in range(2):
+        da = _tangent(rng, a)
+        fd = (O.sgw_value_converged(a + h * da, b, x, y, EPS) - O.sgw_value_converged(a - h * da, b, x, y, EPS)) / (2 * h)
+        assert abs(fd - ga @ da) < 1e-6 * np.abs(ga).sum()
+        db = _tangent(rng, b)
+        fd = (O.sgw_value_converged(a, b + h * db, x, y, EPS) - O.sgw_value_converged(a, b - h * db, x, y, EPS)) / (2 * h)
+        assert abs(fd - gb @ db) < 1e-6 * np.abs(gb).sum()
+
+
+def test_weight_gradient_vanishes_between_isometric_measures():
+    # beta an isometric copy of alpha (SGW = 0, its minimum by Theorem 4.3):
+    # moving either measure's weights along the simplex cannot lower it
+    rng = np.random.default_rng(41)
+    x, a = _measure(rng, 10, 2)
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    perm = rng.permutation(10)
+    y = (x @ R.T + np.array([0.3, -1.2]))[perm]
+    b = a[perm]
+    ga, gb = O.sgw_grad_weights(a, b, x, y, EPS)
+    X, Y = O.centre(x, a), O.centre(y, b)
+    _, pi, _, _ = O.cnt_gw_converged(a, b, X, Y, EPS)
+    scale = np.abs(O.grad_weights(O.sqdist(X, X), O.sqdist(Y, Y), a, b, pi, EPS)).max()
+    assert scale > 1e-1
+    assert np.abs(ga).max() < 1e-8 * scale and np.abs(gb).max() < 1e-8 * scale
+
+
+def test_lifted_weight_gradient_matches_finite_differences():
+    # |x - x'|^1.5 lifted to D = 4 by frozen maps (the weights also move the
+    # re-centring of the features, which the squared distances do not see)
+    rng = np.random.default_rng(44)
+    x, a = _measure(rng, 9, 2)
+    y, b = _measure(rng, 8, 2)
+    lmx, lmy = O.fit_landmarks(x[:7], 1.5, 4), O.fit_landmarks(y[:6], 1.5, 4)
+    tol = 1e-11
+    ga, gb = O.sgw_grad_weights_lifted(a, b, x, y, EPS, lmx, lmy, tol=tol)
+    h = 1e-5
+
+    def val(aa, bb):
+        return O.sgw_value_converged_lifted(aa, bb, x, y, EPS, lmx, lmy, tol)
+
+    da, db = _tangent(rng, a), _tangent(rng, b)
+    fd_a = (val(a + h * da, b) - val(a - h * da, b)) / (2 * h)
+    fd_b = (val(a, b + h * db) - val(a, b - h * db)) / (2 * h)
+    assert abs(fd_a - ga @ da) < 1e-6 * np.abs(ga).sum()
+    assert abs(fd_b - gb @ db) < 1e-6 * np.abs(gb).sum()
