@@ -276,9 +276,10 @@ gw_status gw_sgw(gw_ctx* ctx,
                  const float* y, int64_t m, int dy, const float* b,
                  const gw_params* params, gw_sgw_result* out);
 
-/* Position gradient of the Sinkhorn-GW divergence (Section 4; envelope
-   gradients of Appendix B.6): the three solves of gw_sgw on the raw points,
-   then grad_x = dGW(x, y)/dx - (dGW(x, x)/dx_source + dGW(x, x)/dx_target) / 2
+/* Position and weight gradients of the Sinkhorn-GW divergence (Section 4;
+   envelope gradients of Appendix B.6): the three solves of gw_sgw on the
+   raw points, then
+   grad_x = dGW(x, y)/dx - (dGW(x, x)/dx_source + dGW(x, x)/dx_target) / 2
    and the same for y (device, caller allocated, n x dx and m x dy).  The
    envelope gradient is exact at converged solves.  Each measure keeps its
    side's penalty in every term: with GW_PEN_POWER the pair solve fits the
@@ -286,13 +287,18 @@ gw_status gw_sgw(gw_ctx* ctx,
    self term of x uses x's frozen map on both of its sides and that of y
    uses y's, and every gradient chains through its side's frozen map
    (Algorithm 12 with Algorithm 13), as gw_sgw embeds the three problems.
-   Weight gradients are not provided.  Other inputs, outputs and errors as
-   gw_sgw. */
+   grad_a and grad_b (device, n and m floats, each nullable) receive the
+   weight gradients in the same composition (the self term's source and
+   target weight gradients summed, since it carries the measure's weights in
+   both marginals), each as gw_loss_and_grad gives them: along the simplex,
+   centred so that sum_i a_i grad_a_i = 0.  Other inputs, outputs and errors
+   as gw_sgw. */
 gw_status gw_sgw_grad(gw_ctx* ctx,
                       const float* x, int64_t n, int dx, const float* a,
                       const float* y, int64_t m, int dy, const float* b,
                       const gw_params* params, gw_sgw_result* out,
-                      float* grad_x, float* grad_y);
+                      float* grad_x, float* grad_y,
+                      float* grad_a, float* grad_b);
 
 /* GW barycentre flow (Section 6, "GW Barycenters"): gradient descent on the
    points z (k x d, device, in/out) of gamma_z = sum_i w_i delta_{z_i} (w:

@@ -163,7 +163,7 @@ SIGNATURES = {
     "gw_sgw_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                    ctypes.POINTER(GwParams), ctypes.POINTER(GwSgwResult), ctypes.c_void_p,
-                                   ctypes.c_void_p]),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gw_sgw_barycenter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double,

@@ -295,19 +295,25 @@ class Context:
         return out
 
     def sgw_grad(self, x, a, y, b, eps_start, eps_end=None, n_outer=20, n_inner=50, symmetric=True,
-                 precision="fp32", mode="auto") -> dict:
+                 precision="fp32", mode="auto", weights=False) -> dict:
         """The divergence (gw_sgw fields) and its position gradients
-        (gw_sgw_grad) under the same squared-norm or feature penalty."""
+        (gw_sgw_grad); with weights=True also its weight gradients grad_a,
+        grad_b (centred along the simplex)."""
         x, a, y, b = self._prep(x, a, y, b)
         n, dx = x.shape
         m, dy = y.shape
         prm = make_params(eps_start, eps_end, n_outer, n_inner, symmetric, precision, mode, False, 0.0)
         r = L.GwSgwResult()
         gx, gy = torch.empty_like(x), torch.empty_like(y)
+        ga = torch.empty_like(a) if weights else None
+        gb = torch.empty_like(b) if weights else None
         self._check(self.lib.gw_sgw_grad(self.h, _ptr(x), n, dx, _ptr(a), _ptr(y), m, dy, _ptr(b),
-                                         ctypes.byref(prm), ctypes.byref(r), _ptr(gx), _ptr(gy)))
+                                         ctypes.byref(prm), ctypes.byref(r), _ptr(gx), _ptr(gy), _ptr(ga),
+                                         _ptr(gb)))
         out = {k: getattr(r, k) for k, _ in L.GwSgwResult._fields_}
         out.update({"grad_x": gx, "grad_y": gy})
+        if weights:
+            out.update({"grad_a": ga, "grad_b": gb})
         return out
 
     def sgw_barycenter(self, x, a, y, b, z0, w, lam: float, step: float, n_steps: int, eps_start, eps_end=None,

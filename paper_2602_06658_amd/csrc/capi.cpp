@@ -306,7 +306,7 @@ gw_status gw_sgw(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a,
 
 gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a, const float* y, int64_t m,
                       int dy, const float* b, const gw_params* params, gw_sgw_result* out, float* grad_x,
-                      float* grad_y) {
+                      float* grad_y, float* grad_a, float* grad_b) {
     if (!ctx) return GW_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->c.mu);
     if (!out || !grad_x || !grad_y) return ret(ctx, gwr::fail(GW_EINVAL, "result or gradient is NULL"));
@@ -319,32 +319,41 @@ gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const floa
     float* gxt = c.ws.get_t<float>("sgw.gxt", (size_t)n * dx, &st);
     float* gys = c.ws.get_t<float>("sgw.gys", (size_t)m * dy, &st);
     float* gyt = c.ws.get_t<float>("sgw.gyt", (size_t)m * dy, &st);
+    // weight gradients of the self terms (source and target sides)
+    float* was = grad_a ? c.ws.get_t<float>("sgw.was", (size_t)n, &st) : nullptr;
+    float* wat = grad_a ? c.ws.get_t<float>("sgw.wat", (size_t)n, &st) : nullptr;
+    float* wbs = grad_b ? c.ws.get_t<float>("sgw.wbs", (size_t)m, &st) : nullptr;
+    float* wbt = grad_b ? c.ws.get_t<float>("sgw.wbt", (size_t)m, &st) : nullptr;
     if (!st.good()) return ret(ctx, st);
     auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
-                   const float* wq, gw_result& r, float* gP, float* gQ) -> Status {
+                   const float* wq, gw_result& r, float* gP, float* gQ, float* gwP, float* gwQ) -> Status {
         gwr::Solve solve(c, "s.");
         GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, c.side[0].kind,
                            c.side[1].kind, c.stream));
         while (!solve.done()) GW_TRY(solve.outer_step());
         GW_TRY(solve.finish(&r));
-        return solve.gradients(gP, nullptr, gQ, nullptr);
+        return solve.gradients(gP, gwP, gQ, gwQ);
     };
     // each measure keeps its own side's penalty in every term: the pair
     // solve fits the landmark maps of |x - x'|^p (source on x, target on y),
     // and the self terms use that one map on both of their sides
     gw_result rxy{}, rxx{}, ryy{};
-    st = run(x, n, dx, a, y, m, dy, b, rxy, grad_x, grad_y);
+    st = run(x, n, dx, a, y, m, dy, b, rxy, grad_x, grad_y, grad_a, grad_b);
     if (st.good()) {
         gwr::SideShare share(c, 0, 1);
-        st = run(x, n, dx, a, x, n, dx, a, rxx, gxs, gxt);
+        st = run(x, n, dx, a, x, n, dx, a, rxx, gxs, gxt, was, wat);
     }
     if (st.good()) {
         gwr::SideShare share(c, 1, 0);
-        st = run(y, m, dy, b, y, m, dy, b, ryy, gys, gyt);
+        st = run(y, m, dy, b, y, m, dy, b, ryy, gys, gyt, wbs, wbt);
     }
     if (!st.good()) return ret(ctx, st);
+    // a self term carries its measure's weights in both marginals: its weight
+    // gradient is the sum of its source and target gradients
     if (gwk::launch_sub_half_sum(grad_x, gxs, gxt, n * dx, c.stream) != hipSuccess ||
         gwk::launch_sub_half_sum(grad_y, gys, gyt, m * dy, c.stream) != hipSuccess ||
+        (grad_a && gwk::launch_sub_half_sum(grad_a, was, wat, n, c.stream) != hipSuccess) ||
+        (grad_b && gwk::launch_sub_half_sum(grad_b, wbs, wbt, m, c.stream) != hipSuccess) ||
         hipStreamSynchronize(c.stream) != hipSuccess)
         return ret(ctx, gwr::fail(GW_EDEVICE, "divergence gradient"));
     out->gw_xy = rxy.egw_objective;
