@@ -317,7 +317,12 @@ Status Solve::configure(int64_t n, int dx, int64_t m, int dy, const gw_params& p
             int want = std::max(1, (2048 + mtr - 1) / mtr);
             const size_t per_tile = (size_t)rows_pad * (tw + 2) * sizeof(float);
             const int mem_cap = (int)std::max<size_t>(1, ((size_t)1 << 30) / per_tile);
-            want = std::min(want, std::min(mem_cap, std::max(1, nchc / 32)));
+            // the VALU form (D < 16) has 512-row groups and a payload of at
+            // most 16 columns, so its partials stay small: there the column
+            // tile narrows to one 32-column chunk if the grid needs it (a
+            // 3,000-row problem would otherwise run on a dozen work-groups)
+            const int min_cols = path == 1 ? 1 : 32;
+            want = std::min(want, std::min(mem_cap, std::max(1, nchc / min_cols)));
             bc = (nchc + want - 1) / want;
             mtc = (nchc + bc - 1) / bc;
         };
