@@ -105,12 +105,13 @@ struct CoreF32 {
     }
 };
 
-__device__ __forceinline__ bool should_run(const int* ctl, int run_if) {
+// token: the half-step's number (never 0), which a successful combine stores
+// in CTL_DONE so that the safe kernels of the same half-step skip
+__device__ __forceinline__ bool should_run(const int* ctl, int run_if, int token) {
     if (run_if == RUN_ALWAYS) return true;
     const int mode = ctl[CTL_MODE];
     if (run_if == RUN_STAB) return mode == MODE_STAB;
-    if (run_if == RUN_SAFE) return mode == MODE_SAFE;
-    return mode == MODE_STAB && ctl[CTL_BAD] != 0;  // RUN_RETRY
+    return ctl[CTL_DONE] != token && (mode == MODE_SAFE || ctl[CTL_BAD] != 0);  // RUN_SAFE_OR_RETRY
 }
 
 // Cooperative copy of one 32-column chunk of the B pack into LDS, staged

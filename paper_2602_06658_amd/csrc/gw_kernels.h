@@ -36,6 +36,7 @@ struct Operands {
     const float* V;      // column potentials log2 b_j + kappa g_j, hi
     const float* Vl;     // ... lo
     float kappa;         // log2(e) * 8 / eps
+    int token;           // half-step number, never 0 (launch gates)
 };
 
 struct Partials {
@@ -86,6 +87,7 @@ struct CombineArgs {
     int do_rows, do_cols;
     float step;          // 0.5 (Algorithm 3) or 1.0 (Algorithm 2)
     int is_retry;
+    int token;           // the half-step's number, as in Operands
 };
 hipError_t launch_combine(const CombineArgs& a, int* ctl, int run_if, hipStream_t stream);
 // Combines of several independent problems, 16 per launch; ctls[r] is the

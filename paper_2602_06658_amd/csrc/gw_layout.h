@@ -26,10 +26,15 @@ enum Ctl {
     CTL_NUMERIC = 4,     // sticky: non-finite values seen
     CTL_SAFE_ITERS = 5,  // iterations that ran the safe pass
     CTL_USER = 6,        // user mode: 0 auto, 1 safe, 2 stabilised
+    CTL_DONE = 7,        // token of the last half-step whose combine succeeded
     CTL_WORDS = 8
 };
 enum Mode { MODE_STAB = 0, MODE_SAFE = 1 };
-enum RunIf { RUN_ALWAYS = 0, RUN_STAB = 1, RUN_SAFE = 2, RUN_RETRY = 3 };
+// Launch gates of a half-step: the stabilised pass and its combine run in
+// stabilised mode; the safe pass and its combine run after them unless the
+// half-step is already done, i.e. in safe mode or after a flagged
+// stabilised combine.
+enum RunIf { RUN_ALWAYS = 0, RUN_STAB = 1, RUN_SAFE_OR_RETRY = 2 };
 
 // |log2 (marginal / weight)| above which a stabilised pass is redone safely,
 // and above which the next iteration runs safely.

@@ -35,6 +35,7 @@ struct PassArgs {
     float* cp2;
     const int* ctl;
     int run_if;
+    int token;
     int n_chunks_r, n_chunks_c;
     int rg, bc_chunks;
     int n_mt_r, n_mt_c;
@@ -154,7 +155,7 @@ __device__ __forceinline__ void stab_ring_tile(const PassArgs& p, int rb, int c0
 // partials after the loop.
 template <class C, int RW>
 __device__ __forceinline__ void pass_stab_body(const PassArgs& p, int wg) {
-    if (!should_run(p.ctl, p.run_if)) return;
+    if (!should_run(p.ctl, p.run_if, p.token)) return;
     constexpr int NU = C::UNITS * 64;
     extern __shared__ float dyn[];
     // the wave index through readfirstlane: row-tile bounds derived from it
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__(THREADS) k_pass_stab_batch(PassBatch b) {
 
 template <class C, int RW>
 __device__ __forceinline__ void pass_safe_body(const PassArgs& p, int wg) {
-    if (!should_run(p.ctl, p.run_if)) return;
+    if (!should_run(p.ctl, p.run_if, p.token)) return;
     constexpr int NU = C::UNITS * 64;
     __shared__ uint4 zbuf[2][NU];
     extern __shared__ float dyn[];
@@ -407,6 +408,7 @@ struct ValuArgs {
     float* cp2;
     const int* ctl;
     int run_if;
+    int token;
     int n_pad, m_pad;
     int n_chunks_c;
     int rg, bc_chunks, n_mt_r, n_mt_c;
@@ -429,7 +431,7 @@ __device__ __forceinline__ void valu_load_chunk(float* dst, const ValuArgs& p, i
 
 template <int D, int SAFE>
 __global__ void __launch_bounds__(THREADS) k_pass_valu(ValuArgs p) {
-    if (!should_run(p.ctl, p.run_if)) return;
+    if (!should_run(p.ctl, p.run_if, p.token)) return;
     constexpr int R = D + 3;
     __shared__ float zc[2][32 * R];
     extern __shared__ float dyn[];
@@ -622,6 +624,7 @@ static PassArgs make_pass_args(const Operands& op, const Geometry& g, const Part
     a.cp2 = pp.col2;
     a.ctl = ctl;
     a.run_if = run_if;
+    a.token = op.token;
     a.n_chunks_r = g.n_pad / 32;
     a.n_chunks_c = g.m_pad / 32;
     a.rg = g.rg;
@@ -719,6 +722,7 @@ static hipError_t launch_mfma(const Operands& op, const Geometry& g, const Parti
     a.cp2 = pp.col2;
     a.ctl = ctl;
     a.run_if = run_if;
+    a.token = op.token;
     a.n_chunks_r = g.n_pad / 32;
     a.n_chunks_c = g.m_pad / 32;
     a.rg = g.rg;
@@ -755,6 +759,7 @@ static hipError_t launch_valu_d(const Operands& op, const Geometry& g, const Par
     a.cp2 = pp.col2;
     a.ctl = ctl;
     a.run_if = run_if;
+    a.token = op.token;
     a.n_pad = g.n_pad;
     a.m_pad = g.m_pad;
     a.n_chunks_c = g.m_pad / 32;
@@ -833,7 +838,7 @@ constexpr int COMBINE_UNROLL = 16;
 
 __device__ __forceinline__ void combine_body(const CombineDev& cd, int* ctl, int run_if, int blk, int nblk) {
     const CombineArgs& a = cd.a;
-    if (!should_run(ctl, run_if)) return;
+    if (!should_run(ctl, run_if, a.token)) return;
     const int mode = ctl[CTL_MODE];
     const int user = ctl[CTL_USER];
     const bool safe_parts = a.is_retry || mode == MODE_SAFE;
@@ -962,6 +967,7 @@ __device__ __forceinline__ void combine_body(const CombineDev& cd, int* ctl, int
             const int next = user == 1 ? MODE_SAFE : (user == 2 ? MODE_STAB : (any_unsafe ? MODE_SAFE : MODE_STAB));
             if (safe_parts) atomicAdd(&ctl[CTL_SAFE_ITERS], 1);
             atomicExch(&ctl[CTL_MODE], next);
+            atomicExch(&ctl[CTL_DONE], a.token);
             atomicExch(&ctl[CTL_BAD], 0);
             atomicExch(&ctl[CTL_UNSAFE], 0);
         }

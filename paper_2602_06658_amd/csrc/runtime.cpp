@@ -498,7 +498,11 @@ Status Solve::buffers(bool dry) {
 }
 
 void Solve::make_half(int do_rows, int do_cols, float step, gwk::Operands& op, gwk::CombineArgs& ca) {
+    // a new number per half-step, cycling through [1, 2^30 - 1]: the control
+    // block starts at 0 and only the previous half-step's number can be there
+    half_token_ = half_token_ % 0x3fffffff + 1;
     op = gwk::Operands{};
+    op.token = half_token_;
     op.prec = prec_;
     op.d = D_;
     if (geo_.path == 0) {
@@ -516,6 +520,7 @@ void Solve::make_half(int do_rows, int do_cols, float step, gwk::Operands& op, g
         op.kappa = (float)kappa_;
     }
     ca = gwk::CombineArgs{};
+    ca.token = half_token_;
     ca.rp = rp_;
     ca.rp2 = rp2_;
     ca.cp = cp_;
@@ -549,19 +554,18 @@ void Solve::make_half(int do_rows, int do_cols, float step, gwk::Operands& op, g
 Status Solve::inner_iteration(int k) {
     (void)k;
     gwk::Partials pp{rp_, rp2_, cp_, cp2_};
-    // one half-step: stabilised pass (runs in stabilised mode), safe pass
-    // (runs in safe mode), combine; if the combine flagged the stabilised
-    // sums, the safe pass and a combine run again as the retry
+    // one half-step: stabilised pass and its combine (run in stabilised
+    // mode); then the safe pass and its combine, which run in safe mode and
+    // as the retry when the first combine flagged the stabilised sums
     auto half = [&](int do_rows, int do_cols, float step) -> Status {
         gwk::Operands op;
         gwk::CombineArgs ca;
         make_half(do_rows, do_cols, step, op, ca);
         GW_PROF(GW_PROF_PASS_STAB, gwk::launch_pass(op, geo_, pp, ctl_, RUN_STAB, 0, st_));
-        GW_PROF(GW_PROF_PASS_SAFE, gwk::launch_pass(op, geo_, pp, ctl_, RUN_SAFE, 1, st_));
-        GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_ALWAYS, st_));
-        GW_PROF(GW_PROF_PASS_SAFE, gwk::launch_pass(op, geo_, pp, ctl_, RUN_RETRY, 1, st_));
+        GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_STAB, st_));
+        GW_PROF(GW_PROF_PASS_SAFE, gwk::launch_pass(op, geo_, pp, ctl_, RUN_SAFE_OR_RETRY, 1, st_));
         ca.is_retry = 1;
-        GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_RETRY, st_));
+        GW_PROF(GW_PROF_COMBINE, gwk::launch_combine(ca, ctl_, RUN_SAFE_OR_RETRY, st_));
         return Status::ok();
     };
     if (prm_.symmetric) {

@@ -258,6 +258,7 @@ class Solve {
     int t_ = 0;
     bool done_ = false;
     int pa_ = 0, pb_ = 0;      // pack / potential parities
+    int half_token_ = 0;       // number of the last half-step issued (launch gates)
     double eps_t_ = 0.0, kappa_ = 0.0;
     double asum_ = 1.0, bsum_ = 1.0;
     size_t footprint_ = 0;

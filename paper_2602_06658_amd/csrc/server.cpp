@@ -9,8 +9,8 @@
 //   own, then records an event and hands the request over;
 // * the round thread issues rounds on the context's stream: every active
 //   request advances by one Sinkhorn iteration.  Symmetric MFMA-path requests
-//   go through one batched launch per kernel (pass, safe pass, combine, retry
-//   pass, retry combine) over a table of up to 16 requests whose work-groups
+//   go through one batched launch per kernel (stabilised pass, its combine,
+//   safe or retry pass, its combine) over a table of up to 16 requests whose work-groups
 //   share the GPU; other requests launch their own kernels.  A request's
 //   prologue and covariance run at its own outer-step boundaries.  A finished
 //   request's FP64 check (Appendix A.1's Err) and result readback are queued
@@ -318,10 +318,9 @@ gwr::Status round(gw_server* s, std::vector<Request*>& finished) {
     if (!items.empty()) {
         const int nb = (int)items.size();
         GW_HIP(gwk::launch_pass_batch(items.data(), nb, RUN_STAB, 0, st));
-        GW_HIP(gwk::launch_pass_batch(items.data(), nb, RUN_SAFE, 1, st));
-        GW_HIP(gwk::launch_combine_batch(mains.data(), ctls.data(), nb, RUN_ALWAYS, st));
-        GW_HIP(gwk::launch_pass_batch(items.data(), nb, RUN_RETRY, 1, st));
-        GW_HIP(gwk::launch_combine_batch(retries.data(), ctls.data(), nb, RUN_RETRY, st));
+        GW_HIP(gwk::launch_combine_batch(mains.data(), ctls.data(), nb, RUN_STAB, st));
+        GW_HIP(gwk::launch_pass_batch(items.data(), nb, RUN_SAFE_OR_RETRY, 1, st));
+        GW_HIP(gwk::launch_combine_batch(retries.data(), ctls.data(), nb, RUN_SAFE_OR_RETRY, st));
         for (Request* q : batched) q->solve->advance_parity();
     }
     for (Request* q : s->active) {
