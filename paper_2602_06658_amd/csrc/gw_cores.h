@@ -57,9 +57,13 @@ struct CoreBF16 {
     }
 };
 
+// The last group is the bias unit; its k slots 6 and 7 are zero in both
+// operands (write_bias_a_f32 / write_bias_b_f32), so its fourth slab is not
+// issued: 4 KG - 1 MFMAs per tile, and the sums are the same bit for bit.
 template <int KG>
 struct CoreF32 {
     static constexpr int UNITS = KG;  // groups of four 32x32x2 slabs
+    __device__ static constexpr bool issued(int g, int e) { return !(g == KG - 1 && e == 3); }
     struct A {
         f32x4_t v[KG];
     };
@@ -80,7 +84,8 @@ struct CoreF32 {
 #pragma unroll
         for (int g = 0; g < KG; ++g)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[g][e], b.v[g][e], acc, 0, 0, 0);
+            for (int e = 0; e < 4; ++e)
+                if (issued(g, e)) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[g][e], b.v[g][e], acc, 0, 0, 0);
         return acc;
     }
     __device__ static f32x16_t tile(const A& a, const uint4* lds, int lane) {
@@ -89,7 +94,8 @@ struct CoreF32 {
         for (int g = 0; g < KG; ++g) {
             f32x4_t b = __builtin_bit_cast(f32x4_t, lds[g * 64 + lane]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[g][e], b[e], acc, 0, 0, 0);
+            for (int e = 0; e < 4; ++e)
+                if (issued(g, e)) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[g][e], b[e], acc, 0, 0, 0);
         }
         return acc;
     }
@@ -99,7 +105,8 @@ struct CoreF32 {
         for (int g = 0; g < KG; ++g) {
             f32x4_t b = __builtin_bit_cast(f32x4_t, lds[g * 64 + lane]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b[e], a.v[g][e], acc, 0, 0, 0);
+            for (int e = 0; e < 4; ++e)
+                if (issued(g, e)) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b[e], a.v[g][e], acc, 0, 0, 0);
         }
         return acc;
     }

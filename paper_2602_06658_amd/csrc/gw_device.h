@@ -146,6 +146,8 @@ __device__ __forceinline__ void write_pot_b_bf16(uint16_t* pack, int col, int kb
 }
 
 // F32 bias slots: A: [Uh, 1, n, Ul, 1, 0, 0, 0], B: [1, Vh, ms, 1, Vl, 0, 0, 0].
+// FP32 bias slots: k slots 5 to 7 stay zero (the pass cores skip the MFMA of
+// slots 6 and 7)
 __device__ __forceinline__ void write_bias_a_f32(float* pack, int row, int kb, int groups, float Uh, float Ul,
                                                  float n) {
     float v[8] = {Uh, 1.f, n, Ul, 1.f, 0.f, 0.f, 0.f};
