@@ -29,6 +29,69 @@ static gw_status ret(gw_ctx* ctx, const Status& s) {
     return s.code;
 }
 
+// Independent solves of one call (the three problems of a divergence or of
+// a barycentre step), set up in order on the context's stream, then run
+// with their outer steps interleaved, each on a stream of its own, so that
+// the GPU overlaps the kernels of problems too small to fill it alone.
+// Each solve issues the launches it issues alone, on buffers of its own
+// (its tag), so its result is the same bit for bit; finish() and
+// gradients() wait on each solve's own stream.
+static Status outer_steps_side_by_side(Ctx& c, gwr::Solve* const* solves, int k) {
+    hipStream_t st[Ctx::SIDE_STREAMS];
+    GW_TRY(c.side_streams(k, st));
+    hipEvent_t ready = nullptr;
+    GW_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ready, c.stream);
+    for (int i = 0; e == hipSuccess && i < k; ++i) e = hipStreamWaitEvent(st[i], ready, 0);
+    (void)hipEventDestroy(ready);
+    if (e != hipSuccess) return hip_fail(e, "side-by-side solves");
+    for (int i = 0; i < k; ++i) solves[i]->set_stream(st[i]);
+    Status s;
+    for (bool more = true; more && s.good();) {
+        more = false;
+        for (int i = 0; i < k && s.good(); ++i)
+            if (!solves[i]->done()) {
+                s = solves[i]->outer_step();
+                more = more || !solves[i]->done();
+            }
+    }
+    if (!s.good())
+        for (int i = 0; i < k; ++i) (void)hipStreamSynchronize(st[i]);
+    return s;
+}
+
+// Problems of at most this many entries run side by side; a larger one
+// fills the GPU alone, and the solves then run one after another on one set
+// of buffers (side by side, each holds its own).
+constexpr double SIDE_BY_SIDE_MAX_ENTRIES = 1.0e9;
+
+// cnt (at most 3) independent solves: setup(i, solve) sets solve i up on the
+// context's stream, done(i, solve) collects its result once it has finished.
+template <class Setup, class Done>
+static Status run_independent(Ctx& c, int cnt, bool side_by_side, Setup setup, Done done) {
+    if (!side_by_side) {
+        for (int i = 0; i < cnt; ++i) {
+            gwr::Solve s(c, "s.");
+            GW_TRY(setup(i, s));
+            while (!s.done()) GW_TRY(s.outer_step());
+            GW_TRY(done(i, s));
+        }
+        return Status::ok();
+    }
+    gwr::Solve s0(c, "s0."), s1(c, "s1."), s2(c, "s2.");
+    gwr::Solve* const all[3] = {&s0, &s1, &s2};
+    for (int i = 0; i < cnt; ++i) GW_TRY(setup(i, *all[i]));
+    GW_TRY(outer_steps_side_by_side(c, all, cnt));
+    Status st;
+    for (int i = 0; st.good() && i < cnt; ++i) st = done(i, *all[i]);
+    if (!st.good()) {  // the others' work must end before their buffers are reused
+        hipStream_t ss[Ctx::SIDE_STREAMS];
+        if (c.side_streams(cnt, ss).good())
+            for (int i = 0; i < cnt; ++i) (void)hipStreamSynchronize(ss[i]);
+    }
+    return st;
+}
+
 extern "C" {
 
 gw_status gw_create(gw_ctx** out, int device, void* hip_stream, size_t workspace_limit_bytes) {
@@ -281,19 +344,24 @@ gw_status gw_sgw(gw_ctx* ctx, const float* x, int64_t n, int dx, const float* a,
     if (st.good()) st = gwr::lift_side(c, 1, y, m, dy, b, Y, m_pad, "sgw.");
     if (!st.good()) return ret(ctx, st);
     gwr::FeatureSides guard(c);
-    auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
-                   const float* wq, gw_result& r) -> Status {
-        gwr::Solve solve(c, "s.");
-        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, GW_PEN_FEATURES,
-                           GW_PEN_FEATURES, c.stream));
-        while (!solve.done()) GW_TRY(solve.outer_step());
-        return solve.finish(&r);
-    };
-    gw_result rxy{}, rxx{}, ryy{};
-    st = run(X, n, D, a, Y, m, E, b, rxy);
-    if (st.good()) st = run(X, n, D, a, X, n, D, a, rxx);
-    if (st.good()) st = run(Y, m, E, b, Y, m, E, b, ryy);
+    // (alpha, beta), (alpha, alpha), (beta, beta)
+    const float* P[3] = {X, X, Y};
+    const float* Q[3] = {Y, X, Y};
+    const float* wp[3] = {a, a, b};
+    const float* wq[3] = {b, a, b};
+    const int64_t np[3] = {n, n, m}, nq[3] = {m, n, m};
+    const int dp[3] = {D, D, E}, dq[3] = {E, D, E};
+    gw_result r[3] = {};
+    const double most = std::max({(double)n * m, (double)n * n, (double)m * m});
+    st = run_independent(
+        c, 3, most <= SIDE_BY_SIDE_MAX_ENTRIES,
+        [&](int i, gwr::Solve& s) {
+            return s.setup(P[i], np[i], dp[i], wp[i], Q[i], nq[i], dq[i], wq[i], *params, nullptr, nullptr, nullptr,
+                           GW_PEN_FEATURES, GW_PEN_FEATURES, c.stream);
+        },
+        [&](int i, gwr::Solve& s) { return s.finish(&r[i]); });
     if (!st.good()) return ret(ctx, st);
+    const gw_result &rxy = r[0], &rxx = r[1], &ryy = r[2];
     out->gw_xy = rxy.egw_objective;
     out->gw_xx = rxx.egw_objective;
     out->gw_yy = ryy.egw_objective;
@@ -325,29 +393,42 @@ gw_status gw_sgw_grad(gw_ctx* ctx, const float* x, int64_t n, int dx, const floa
     float* wbs = grad_b ? c.ws.get_t<float>("sgw.wbs", (size_t)m, &st) : nullptr;
     float* wbt = grad_b ? c.ws.get_t<float>("sgw.wbt", (size_t)m, &st) : nullptr;
     if (!st.good()) return ret(ctx, st);
-    auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
-                   const float* wq, gw_result& r, float* gP, float* gQ, float* gwP, float* gwQ) -> Status {
-        gwr::Solve solve(c, "s.");
-        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, c.side[0].kind,
-                           c.side[1].kind, c.stream));
-        while (!solve.done()) GW_TRY(solve.outer_step());
-        GW_TRY(solve.finish(&r));
-        return solve.gradients(gP, gwP, gQ, gwQ);
-    };
     // each measure keeps its own side's penalty in every term: the pair
     // solve fits the landmark maps of |x - x'|^p (source on x, target on y),
-    // and the self terms use that one map on both of their sides
-    gw_result rxy{}, rxx{}, ryy{};
-    st = run(x, n, dx, a, y, m, dy, b, rxy, grad_x, grad_y, grad_a, grad_b);
-    if (st.good()) {
-        gwr::SideShare share(c, 0, 1);
-        st = run(x, n, dx, a, x, n, dx, a, rxx, gxs, gxt, was, wat);
-    }
-    if (st.good()) {
-        gwr::SideShare share(c, 1, 0);
-        st = run(y, m, dy, b, y, m, dy, b, ryy, gys, gyt, wbs, wbt);
-    }
+    // and the self terms use that one map on both of their sides (in their
+    // setups, which lift, and in their gradients, which chain through it)
+    const float* P[3] = {x, x, y};
+    const float* Q[3] = {y, x, y};
+    const float* wp[3] = {a, a, b};
+    const float* wq[3] = {b, a, b};
+    const int64_t np[3] = {n, n, m}, nq[3] = {m, n, m};
+    const int dp[3] = {dx, dx, dy}, dq[3] = {dy, dx, dy};
+    float* gP[3] = {grad_x, gxs, gys};
+    float* gQ[3] = {grad_y, gxt, gyt};
+    float* gwP[3] = {grad_a, was, wbs};
+    float* gwQ[3] = {grad_b, wat, wbt};
+    auto share = [&](int i) {
+        std::unique_ptr<gwr::SideShare> sh;
+        if (i == 1) sh.reset(new gwr::SideShare(c, 0, 1));
+        if (i == 2) sh.reset(new gwr::SideShare(c, 1, 0));
+        return sh;
+    };
+    gw_result r[3] = {};
+    const double most = std::max({(double)n * m, (double)n * n, (double)m * m});
+    st = run_independent(
+        c, 3, most <= SIDE_BY_SIDE_MAX_ENTRIES,
+        [&](int i, gwr::Solve& s) {
+            auto sh = share(i);
+            return s.setup(P[i], np[i], dp[i], wp[i], Q[i], nq[i], dq[i], wq[i], *params, nullptr, nullptr, nullptr,
+                           c.side[0].kind, c.side[1].kind, c.stream);
+        },
+        [&](int i, gwr::Solve& s) -> Status {
+            auto sh = share(i);
+            GW_TRY(s.finish(&r[i]));
+            return s.gradients(gP[i], gwP[i], gQ[i], gwQ[i]);
+        });
     if (!st.good()) return ret(ctx, st);
+    const gw_result &rxy = r[0], &rxx = r[1], &ryy = r[2];
     // a self term carries its measure's weights in both marginals: its weight
     // gradient is the sum of its source and target gradients
     if (gwk::launch_sub_half_sum(grad_x, gxs, gxt, n * dx, c.stream) != hipSuccess ||
@@ -475,28 +556,43 @@ gw_status gw_sgw_barycenter(gw_ctx* ctx, const float* x, int64_t n, const float*
     float* gs = c.ws.get_t<float>("bc.gs", (size_t)k * d, &st);
     float* gt = c.ws.get_t<float>("bc.gt", (size_t)k * d, &st);
     if (!st.good()) return ret(ctx, st);
-    auto run = [&](const float* P, int64_t np, const float* wp, const float* Q, int64_t nq, const float* wq,
-                   double* egw, float* gP, float* gQ) -> Status {
-        gwr::Solve solve(c, "s.");
-        GW_TRY(solve.setup(P, np, d, wp, Q, nq, d, wq, *params, nullptr, nullptr, nullptr, kind, kind, c.stream));
-        while (!solve.done()) GW_TRY(solve.outer_step());
-        gw_result r{};
-        GW_TRY(solve.finish(&r));
-        *egw = r.egw_objective;
-        if (gP || gQ) GW_TRY(solve.gradients(gP, nullptr, gQ, nullptr));
-        return Status::ok();
+    // one problem: P against Q with weights wp and wq, and where to write
+    // the gradients of P and Q (null: not wanted)
+    struct Problem {
+        const float *P, *wp, *Q, *wq;
+        int64_t np, nq;
+        float *gP, *gQ;
+    };
+    const double most = std::max({(double)k * n, (double)k * m, (double)k * k, (double)n * n, (double)m * m});
+    auto run = [&](const Problem* pr, int cnt, double* egw) -> Status {
+        return run_independent(
+            c, cnt, most <= SIDE_BY_SIDE_MAX_ENTRIES,
+            [&](int i, gwr::Solve& s) {
+                return s.setup(pr[i].P, pr[i].np, d, pr[i].wp, pr[i].Q, pr[i].nq, d, pr[i].wq, *params, nullptr,
+                               nullptr, nullptr, kind, kind, c.stream);
+            },
+            [&](int i, gwr::Solve& s) -> Status {
+                gw_result r{};
+                GW_TRY(s.finish(&r));
+                egw[i] = r.egw_objective;
+                if (pr[i].gP || pr[i].gQ) GW_TRY(s.gradients(pr[i].gP, nullptr, pr[i].gQ, nullptr));
+                return Status::ok();
+            });
     };
     // GW(alpha, alpha) and GW(beta, beta) do not move with z
-    double eaa = 0.0, ebb = 0.0;
-    st = run(x, n, a, x, n, a, &eaa, nullptr, nullptr);
-    if (st.good()) st = run(y, m, b, y, m, b, &ebb, nullptr, nullptr);
+    double eself[2] = {0.0, 0.0};
+    const Problem selfs[2] = {{x, a, x, a, n, n, nullptr, nullptr}, {y, b, y, b, m, m, nullptr, nullptr}};
+    st = run(selfs, 2, eself);
+    const double eaa = eself[0], ebb = eself[1];
     for (int s = 0; st.good() && s <= n_steps; ++s) {
         const bool last = s == n_steps;
-        double ezx = 0.0, ezy = 0.0, ezz = 0.0;
-        st = run(z, k, w, x, n, a, &ezx, last ? nullptr : g1, nullptr);
-        if (st.good()) st = run(z, k, w, y, m, b, &ezy, last ? nullptr : g2, nullptr);
-        if (st.good()) st = run(z, k, w, z, k, w, &ezz, last ? nullptr : gs, last ? nullptr : gt);
+        double ez[3] = {0.0, 0.0, 0.0};
+        const Problem probs[3] = {{z, w, x, a, k, n, last ? nullptr : g1, nullptr},
+                                  {z, w, y, b, k, m, last ? nullptr : g2, nullptr},
+                                  {z, w, z, w, k, k, last ? nullptr : gs, last ? nullptr : gt}};
+        st = run(probs, 3, ez);
         if (!st.good()) break;
+        const double ezx = ez[0], ezy = ez[1], ezz = ez[2];
         if (objective)
             objective[s] = (1.0 - lambda) * (ezx - 0.5 * (ezz + eaa)) + lambda * (ezy - 0.5 * (ezz + ebb));
         if (!last && gwk::launch_bary_step(z, k, d, w, g1, g2, gs, gt, (float)lambda, (float)step, c.stream) !=

@@ -119,9 +119,20 @@ void* Ctx::host_stage(size_t bytes, Status* st) {
     return stage_;
 }
 
+Status Ctx::side_streams(int k, hipStream_t* out) {
+    if (k < 1 || k > SIDE_STREAMS) return fail(GW_EINVAL, "side-by-side solves: 1 to 3 streams");
+    for (int i = 0; i < k; ++i) {
+        if (!side_[i]) GW_HIP(hipStreamCreateWithFlags(&side_[i], hipStreamNonBlocking));
+        out[i] = side_[i];
+    }
+    return Status::ok();
+}
+
 Ctx::~Ctx() {
     stepped.reset();
     if (stage_ && stage_owned_) (void)hipHostFree(stage_);
+    for (hipStream_t s : side_)
+        if (s) (void)hipStreamDestroy(s);
 }
 
 hipEvent_t Profiler::take() {

@@ -155,9 +155,15 @@ struct Ctx {
         stage_bytes_ = bytes;
         stage_owned_ = false;
     }
+    // The first k (at most SIDE_STREAMS) streams on which one call runs
+    // independent solves side by side; created on first use, default
+    // priority, destroyed with the context.
+    static constexpr int SIDE_STREAMS = 3;
+    Status side_streams(int k, hipStream_t* out);
     ~Ctx();
 
    private:
+    hipStream_t side_[SIDE_STREAMS] = {};
     void* stage_ = nullptr;
     size_t stage_bytes_ = 0;
     bool stage_owned_ = true;
