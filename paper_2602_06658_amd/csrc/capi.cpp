@@ -493,29 +493,45 @@ static Status bary_lifted(gwr::Ctx& c, const float* x, int64_t n, const float* a
     };
     GW_TRY(lift_with(ca, x, n, a, Xa));
     GW_TRY(lift_with(cb, y, m, b, Xb));
-    auto run = [&](const float* P, int64_t np, int dp, const float* wp, const float* Q, int64_t nq, int dq,
-                   const float* wq, double* egw, float* gP, float* gQ) -> Status {
-        gwr::FeatureSides fs(c);
-        gwr::Solve solve(c, "s.");
-        GW_TRY(solve.setup(P, np, dp, wp, Q, nq, dq, wq, *params, nullptr, nullptr, nullptr, GW_PEN_FEATURES,
-                           GW_PEN_FEATURES, c.stream));
-        while (!solve.done()) GW_TRY(solve.outer_step());
-        gw_result r{};
-        GW_TRY(solve.finish(&r));
-        *egw = r.egw_objective;
-        if (gP || gQ) GW_TRY(solve.gradients(gP, nullptr, gQ, nullptr));
-        return Status::ok();
+    // problems on the lifted features: P (dimension dp) against Q (dq), and
+    // where to write the feature gradients of P and Q (null: not wanted)
+    struct Problem {
+        const float *P, *wp, *Q, *wq;
+        int64_t np, nq;
+        int dp, dq;
+        float *gP, *gQ;
     };
-    double eaa = 0.0, ebb = 0.0;
-    GW_TRY(run(Xa, n, Da, a, Xa, n, Da, a, &eaa, nullptr, nullptr));
-    GW_TRY(run(Xb, m, Da, b, Xb, m, Da, b, &ebb, nullptr, nullptr));
+    const double most = std::max({(double)k * n, (double)k * m, (double)k * k, (double)n * n, (double)m * m});
+    auto run = [&](const Problem* pr, int cnt, double* egw) -> Status {
+        gwr::FeatureSides fs(c);
+        return run_independent(
+            c, cnt, most <= SIDE_BY_SIDE_MAX_ENTRIES,
+            [&](int i, gwr::Solve& s) {
+                return s.setup(pr[i].P, pr[i].np, pr[i].dp, pr[i].wp, pr[i].Q, pr[i].nq, pr[i].dq, pr[i].wq, *params,
+                               nullptr, nullptr, nullptr, GW_PEN_FEATURES, GW_PEN_FEATURES, c.stream);
+            },
+            [&](int i, gwr::Solve& s) -> Status {
+                gw_result r{};
+                GW_TRY(s.finish(&r));
+                egw[i] = r.egw_objective;
+                if (pr[i].gP || pr[i].gQ) GW_TRY(s.gradients(pr[i].gP, nullptr, pr[i].gQ, nullptr));
+                return Status::ok();
+            });
+    };
+    double eself[2] = {0.0, 0.0};
+    const Problem selfs[2] = {{Xa, a, Xa, a, n, n, Da, Da, nullptr, nullptr},
+                              {Xb, b, Xb, b, m, m, Da, Da, nullptr, nullptr}};
+    GW_TRY(run(selfs, 2, eself));
+    const double eaa = eself[0], ebb = eself[1];
     for (int s = 0; s <= n_steps; ++s) {
         const bool last = s == n_steps;
         GW_TRY(lift_with(cz, z, k, w, Zf));
-        double ezx = 0.0, ezy = 0.0, ezz = 0.0;
-        GW_TRY(run(Zf, k, Dz, w, Xa, n, Da, a, &ezx, last ? nullptr : gf[0], nullptr));
-        GW_TRY(run(Zf, k, Dz, w, Xb, m, Da, b, &ezy, last ? nullptr : gf[1], nullptr));
-        GW_TRY(run(Zf, k, Dz, w, Zf, k, Dz, w, &ezz, last ? nullptr : gf[2], last ? nullptr : gf[3]));
+        double ez[3] = {0.0, 0.0, 0.0};
+        const Problem probs[3] = {{Zf, w, Xa, a, k, n, Dz, Da, last ? nullptr : gf[0], nullptr},
+                                  {Zf, w, Xb, b, k, m, Dz, Da, last ? nullptr : gf[1], nullptr},
+                                  {Zf, w, Zf, w, k, k, Dz, Dz, last ? nullptr : gf[2], last ? nullptr : gf[3]}};
+        GW_TRY(run(probs, 3, ez));
+        const double ezx = ez[0], ezy = ez[1], ezz = ez[2];
         if (objective)
             objective[s] = (1.0 - lambda) * (ezx - 0.5 * (ezz + eaa)) + lambda * (ezy - 0.5 * (ezz + ebb));
         if (last) break;
