@@ -270,7 +270,11 @@ typedef struct {
    times on the lifted features, (x, y), (x, x) and (y, y), from Gamma_0 = 0
    with the same params; each GW_eps is the EGW objective at the schedule's
    last eps.  Same inputs and errors as gw_solve; params->use_init_potentials
-   is rejected (GW_EINVAL). */
+   is rejected (GW_EINVAL).  When no problem has more than 1e9 entries, the
+   three solves run side by side, each on a stream the context creates once
+   (default priority) and on device buffers of its own; the results are
+   those of the solves run one after another, bit for bit, and the call
+   returns once all three have finished. */
 gw_status gw_sgw(gw_ctx* ctx,
                  const float* x, int64_t n, int dx, const float* a,
                  const float* y, int64_t m, int dy, const float* b,
@@ -308,7 +312,7 @@ gw_status gw_sgw_grad(gw_ctx* ctx,
    the n_steps steps runs Algorithm 1 on (z, x), (z, y) and (z, z) with params,
    takes the divergence's position gradient (gw_sgw_grad) and moves
    z_i -= step / w_i * gradient_i; GW_eps(alpha, alpha) and GW_eps(beta, beta)
-   are solved once.  objective (host, n_steps + 1 values, nullable) receives
+   are solved once.  The solves of a step run side by side as in gw_sgw.  objective (host, n_steps + 1 values, nullable) receives
    the objective before each step and after the last.  Penalties: the same
    GW_PEN_SQEUCLID or GW_PEN_FEATURES on both sides, or GW_PEN_POWER on both
    sides, where z is embedded by a landmark map with side 0's settings
