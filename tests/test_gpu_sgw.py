@@ -101,3 +101,28 @@ def test_sgw_vanishes_between_isometric_measures(gw):
     print(res)
     assert res["gw_xx"] > 1e-2
     assert abs(res["sgw"]) <= 1e-5 * res["gw_xx"]
+
+
+@pytest.mark.parametrize("kind", ["sqeuclid", "features"])
+def test_sgw_terms_do_not_depend_on_the_other_problems(gw, kind):
+    """The three solves of a divergence run side by side, each on a stream
+    and buffers of its own: the (x, x) term must come out the same, bit for
+    bit, whatever the other measure is and on whichever side x is."""
+    if kind == "sqeuclid":
+        _, x, a = _measure(48, 900, 3)
+        _, y1, b1 = _measure(49, 700, 3)
+        _, y2, b2 = _measure(50, 1200, 3)
+    else:
+        x, y1, y2 = (f32(scale_features(s, n, 32, decay=1.0) * 2.0) for s, n in ((51, 900), (52, 700), (53, 1200)))
+        a, b1, b2 = (np.full(n, 1.0 / n) for n in (900, 700, 1200))
+    ctx = gw.Context()
+    if kind == "features":
+        ctx.set_penalty(2, "features")
+    prec = "bf16" if kind == "features" else "fp32"
+    r1 = ctx.sgw(dev(x), dev(a), dev(y1), dev(b1), 0.5, 0.5, 5, 60, precision=prec)
+    r2 = ctx.sgw(dev(x), dev(a), dev(y2), dev(b2), 0.5, 0.5, 5, 60, precision=prec)
+    r3 = ctx.sgw(dev(y2), dev(b2), dev(x), dev(a), 0.5, 0.5, 5, 60, precision=prec)
+    print(kind, r1["gw_xx"], r2["gw_xx"], r3["gw_yy"], r1["gw_xy"], r2["gw_xy"])
+    assert r1["gw_xx"] == r2["gw_xx"] == r3["gw_yy"]
+    assert r2["gw_yy"] == r3["gw_xx"]
+    assert r1["gw_xy"] != r2["gw_xy"]
