@@ -745,6 +745,28 @@ __device__ __forceinline__ float pack_elem(const void* pack, int prec, int units
 // 4 x 4 block of entries (rows 4 ty + u, columns 4 tx + v).  The reduction
 // scratch reuses the operand tiles' LDS.
 constexpr int CK_T = 64, CK_KB = 40, CKM = 2048;
+static_assert(CK_KB % 8 == 0, "K blocks hold whole 8-k groups");
+
+// Eight consecutive k (k0 a multiple of 8) of one packed row as floats, the
+// values pack_elem gives: one 16-byte unit of a BF16 pack, or the two units
+// (lanes r and r + 32) of an FP32 pack that hold the even and odd k.  Every
+// pack's K is a multiple of 8, so a group is either whole or past K.
+__device__ __forceinline__ void pack_group8(const void* pack, int prec, int units, int row, int k0, float* v) {
+    if (prec == PREC_F32) {
+        const float4 ev = *reinterpret_cast<const float4*>((const float*)pack + f32_pack_off(row, k0, units));
+        const float4 od = *reinterpret_cast<const float4*>((const float*)pack + f32_pack_off(row, k0 + 1, units));
+        v[0] = ev.x; v[1] = od.x; v[2] = ev.y; v[3] = od.y;
+        v[4] = ev.z; v[5] = od.z; v[6] = ev.w; v[7] = od.w;
+        return;
+    }
+    const uint4 u = *reinterpret_cast<const uint4*>((const uint16_t*)pack + bf16_pack_off(row, k0, units));
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        v[2 * t] = bf16_bits_to_f32((uint16_t)(w[t] & 0xffffu));
+        v[2 * t + 1] = bf16_bits_to_f32((uint16_t)(w[t] >> 16));
+    }
+}
 
 // The macro tile's side: CKM, halved (down to one 64 x 64 sub-tile) while the
 // grid would have fewer than 512 work-groups, so that problems of a few
@@ -795,12 +817,17 @@ __global__ void __launch_bounds__(256) k_check64_tiles(int prec, int units, int 
                 for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
             for (int k0 = 0; k0 < K; k0 += CK_KB) {
                 __syncthreads();
-                for (int e = tid; e < CK_T * CK_KB; e += 256) {
-                    const int rr = e / CK_KB, kk = e - rr * CK_KB;
-                    const int64_t i = r0 + rr, j = c0 + rr;
-                    const int k = k0 + kk;
-                    As[rr][kk] = (i < n && k < K) ? pack_elem(A, prec, units, (int)i, k) : 0.f;
-                    Bs[rr][kk] = (j < m && k < K) ? pack_elem(B, prec, units, (int)j, k) : 0.f;
+                // one thread per (row, 8-k group) of each operand
+                for (int e = tid; e < 2 * CK_T * (CK_KB / 8); e += 256) {
+                    const int op = e / (CK_T * (CK_KB / 8)), f = e - op * (CK_T * (CK_KB / 8));
+                    const int rr = f / (CK_KB / 8), q = f - rr * (CK_KB / 8);
+                    const int64_t row = (op ? c0 : r0) + rr;
+                    const int k = k0 + 8 * q;
+                    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (row < (op ? m : n) && k < K) pack_group8(op ? B : A, prec, units, (int)row, k, v);
+                    float* dst = op ? &Bs[rr][8 * q] : &As[rr][8 * q];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) dst[t] = v[t];
                 }
                 if (tid < CK_T) lbs[tid] = c0 + tid < m ? lb2[c0 + tid] : 0.f;
                 __syncthreads();
@@ -897,6 +924,7 @@ hipError_t launch_check64(int prec, int d, const void* Arows, const void* Bcols,
                           hipStream_t stream) {
     const int K = pack_k(prec, d);
     const int units = pack_units(prec, d);
+    if (K % 8 != 0) return hipErrorInvalidValue;  // the tiles load whole 8-k groups
     const int span = check_span(n, m);
     const int n_rt = (int)((n + span - 1) / span), n_ct = (int)((m + span - 1) / span);
     double* rpart = part;
