@@ -84,10 +84,10 @@ __global__ void __launch_bounds__(KP_THREADS) k_kpca_cm(const float* __restrict_
 
 // Wide form for blocks of more than 16 columns: a workgroup of 6 waves covers
 // 256 rows x 96 columns.  The costs of a 256 x 32 tile are computed once into
-// LDS (instead of once per 16-column group); wave w owns columns 16 w..16 w+15
-// of the workgroup's 96 and thread t of the wave rows 4 t..4 t+3, so the four
+// LDS (instead of once per column group); wave w owns columns 8 w..8 w+7 of
+// the workgroup's 96 and thread t of the wave rows 4 t..4 t+3, so the four
 // costs of a point are one 16-byte LDS read and the M values are broadcasts.
-constexpr int KW_ROWS = 256, KW_COLS = 96, KW_TJ = 32, KW_THREADS = 384;
+constexpr int KW_ROWS = 256, KW_COLS = 96, KW_TJ = 32, KW_CPW = 6, KW_THREADS = 64 * (KW_COLS / KW_CPW);
 
 template <int MAXD>
 __global__ void __launch_bounds__(KW_THREADS) k_kpca_cm_wide(const float* __restrict__ x, int64_t n, int d,
@@ -106,11 +106,11 @@ __global__ void __launch_bounds__(KW_THREADS) k_kpca_cm_wide(const float* __rest
         const int r = e / MAXD, dd = e - r * MAXD;
         xr[e] = (row0 + r < n && dd < d) ? x[(row0 + r) * d + dd] : 0.f;
     }
-    double acc[4][16];
+    double acc[4][KW_CPW];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc[r][cc] = 0.0;
+        for (int cc = 0; cc < KW_CPW; ++cc) acc[r][cc] = 0.0;
     for (int64_t j0 = 0; j0 < n; j0 += KW_TJ) {
         __syncthreads();
         for (int e = tid; e < KW_TJ * MAXD; e += KW_THREADS) {
@@ -141,9 +141,9 @@ __global__ void __launch_bounds__(KW_THREADS) k_kpca_cm_wide(const float* __rest
         for (int jj = 0; jj < KW_TJ; ++jj) {
             const float4 c4 = *(const float4*)&cs[jj * KW_ROWS + lane * 4];
             const double cr[4] = {(double)c4.x, (double)c4.y, (double)c4.z, (double)c4.w};
-            const double* mrow = &ms[jj * KW_COLS + grp * 16];
+            const double* mrow = &ms[jj * KW_COLS + grp * KW_CPW];
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc) {
+            for (int cc = 0; cc < KW_CPW; ++cc) {
                 const double mv = mrow[cc];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc[r][cc] = fma(cr[r], mv, acc[r][cc]);
@@ -151,8 +151,8 @@ __global__ void __launch_bounds__(KW_THREADS) k_kpca_cm_wide(const float* __rest
         }
     }
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) {
-        const int col = col0 + grp * 16 + cc;
+    for (int cc = 0; cc < KW_CPW; ++cc) {
+        const int col = col0 + grp * KW_CPW + cc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t i = row0 + lane * 4 + r;
